@@ -1,0 +1,196 @@
+/*
+ * at.h -- C ABI of libat, the MI355X (gfx950) implementation of the
+ * asynchrony-tolerant (AT) multi-stage Runge-Kutta step of Kumari et al.,
+ * "Evaluation of finite difference based asynchronous partial differential
+ * equations solver for reacting flows" (arXiv:2204.01133).
+ *
+ * The operation (Sec. 2.1-2.3 and Sec. 3 of the paper): a periodic 1D problem
+ * of N points is split into P processing elements (PEs).  Every step draws a
+ * delay k~ in {0..kmax} per PE (Sec. 2.1; probabilities of Table dels) and
+ * advances all S stages of an explicit RK scheme (eq. rk1).  At PE-boundary
+ * halo points each stage uses the synchronous stage values of the delayed
+ * levels n-k~-l, l = 0..J-1, extrapolated in time to level n (Table A for the
+ * central schemes, eqs. atRecon/beta2AT* for AT-WENO), the multi-stage
+ * procedure of Sec. 2.3.  Interior points use the standard central
+ * difference (order 2, 4 or 8) or WENO5-JS with local Lax-Friedrichs flux
+ * splitting (eqs. Csplit, wender, omg, betaS, idRec).
+ *
+ * Memory and streams: the caller owns every device buffer and the HIP stream.
+ * at_init computes the size of ONE device workspace; the caller allocates it
+ * (e.g. with torch) and hands it over with at_bind.  The library never
+ * allocates or frees device memory.  Calls that take the context are
+ * stream-ordered and asynchronous unless stated; one context per stream, no
+ * internal locking.  Host pointers may be pageable.
+ *
+ * Errors: every int-returning entry point returns AT_OK (0) or a negative
+ * AT_E* code; no exception crosses the ABI.  at_strerror gives a static
+ * string, at_last_error the context's last detailed message.
+ */
+#ifndef AT_H
+#define AT_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum at_status {
+    AT_OK = 0,
+    AT_EINVAL = -1,        /* bad descriptor, size or argument                          */
+    AT_EUNSUPPORTED = -2,  /* valid combination this build does not run (e.g. PE too big) */
+    AT_ESTATE = -3,        /* call order (not bound, state not set, mid-step)           */
+    AT_EHIP = -4,          /* HIP runtime error; text in at_last_error                  */
+    AT_ESTALE = -5,        /* delay override asks for data older than the ring holds    */
+    AT_ERANGE = -6         /* step or problem index outside what is held                */
+};
+
+enum at_pde { AT_PDE_ADV_DIFF = 0, AT_PDE_ADR_LOGISTIC = 1, AT_PDE_BURGERS = 2, AT_PDE_EULER = 3,
+              AT_PDE_REACTIVE_EULER = 4, AT_PDE_REACTIVE_NS = 5 };
+enum at_scheme { AT_FD2 = 0, AT_FD4 = 1, AT_FD8 = 2, AT_WENO5 = 3 };
+enum at_mode { AT_SYNC = 0, AT_AS = 1, AT_AT = 2 };
+enum at_rk { AT_FE = 0, AT_RK2 = 1, AT_SSPRK3 = 2, AT_RK4 = 3 };
+enum at_granularity { AT_PER_PE = 0, AT_PER_PE_SIDE = 1, AT_PER_BOUNDARY = 2 };
+enum at_precision { AT_FP64 = 0, AT_FP32C = 1, AT_FP32 = 2 };
+
+/*
+ * One periodic problem (plain old data).
+ *   pde/scheme   PDE and spatial scheme; central FD with advection-diffusion(-
+ *                logistic) and one-step-chemistry Navier-Stokes, WENO5 with
+ *                linear advection (alpha = 0), Burgers, Euler, reactive Euler.
+ *   mode         AT (extrapolated delayed halos), AS (standard scheme on the
+ *                delayed level, eq. async-fde / asweno), SYNC (delay 0).
+ *   rk           Butcher tableau: forward Euler, RK2 (eq. rk2), SSP-RK3, RK4.
+ *   granularity  one delay per PE (both sides), per PE side, or per boundary.
+ *   precision    FP64; FP32C = FP32 arithmetic with the state kept as a
+ *                compensated hi+lo pair (TwoSum update) and FP64 temperature
+ *                inversion and Arrhenius rate; FP32 = the same without
+ *                persisting lo between steps.
+ *   kmax         largest delay (0..15).  n_cdf = 0: uniform on {0..kmax};
+ *                n_cdf = kmax: delay k is the number of thresholds cdf[i]
+ *                (i < kmax, 2^32 scale) at or below the draw's top 32 bits.
+ *   at_levels    J, time levels of the AT extrapolation (0: 3 for FD4/FD8,
+ *                2 for FD2 and WENO5).
+ *   n, p         points and PEs, 1 <= p <= n; PE k owns [floor(kn/p), floor((k+1)n/p)).
+ *   x0, lx, dt   grid x_j = x0 + (j + 1/2) lx/n; constant time step.
+ *   c, alpha, r  advection speed, diffusivity, logistic rate.
+ *   gamma, q, ea, b, mu, pr, le  gas constant ratio (R = 1), heat release,
+ *                activation energy, pre-exponential factor, viscosity, Prandtl
+ *                and Lewis numbers (one-step chemistry, E = T/(gamma-1) +
+ *                u^2/2 + q Y, rate -b rho Y exp(-ea/T)).
+ *   weno_eps     epsilon of the WENO weights (eq. omg), e.g. 1e-6.
+ *   seed, problem_id  key of the counter-based delay generator (SplitMix64
+ *                finaliser; draw for (step, pe, side) as in the oracle docs).
+ */
+typedef struct at_problem_desc {
+    int32_t pde, scheme, mode, rk, granularity, precision;
+    int32_t kmax, at_levels, n_cdf, pad0;
+    int64_t n;
+    int32_t p, pad1;
+    uint64_t cdf[16];
+    double x0, lx, dt;
+    double c, alpha, r, gamma, q, ea, b, mu, pr, le, weno_eps;
+    uint64_t seed;
+    int64_t problem_id;
+} at_problem_desc;
+
+/*
+ * Launch options (all 0 = defaults chosen by the planner).
+ *   tile_points     largest number of points of one tile (work item); PEs are
+ *                   packed whole into tiles, a PE may not exceed it.
+ *   persistent      batched form: 1 = persistent grid (grid-stride over the
+ *                   work list), 0 = one workgroup per tile, -1 = planner's choice.
+ *   grid_per_cu     persistent grid size = grid_per_cu x 256 compute units.
+ *   graph_steps     batched form: steps per captured HIP graph (0 = plain launches).
+ *   xcd_remap       1 = XCD-aware tile order (consecutive tiles on one XCD).
+ *   log_steps       capacity, in steps, of the device delay log (0 = off).
+ *   override_steps  capacity, in steps, of the delay-override buffer (0 = off).
+ *   stage_api       1 = reserve the stage buffers that at_rk_stage needs.
+ */
+typedef struct at_run_opts {
+    int32_t tile_points, persistent, grid_per_cu, graph_steps;
+    int32_t xcd_remap, log_steps, override_steps, stage_api;
+    int32_t reserved[8];
+} at_run_opts;
+
+typedef struct at_ctx at_ctx;
+
+/* Validate the problems, plan tiles, ring and work list; no device memory is
+ * touched.  *workspace_bytes receives the size of the device workspace.
+ * Errors: AT_EINVAL (descriptor), AT_EUNSUPPORTED (e.g. a PE larger than a tile). */
+int at_init(const at_problem_desc* probs, int n_probs, const at_run_opts* opts, at_ctx** out,
+            size_t* workspace_bytes);
+
+/* Hand over the caller-owned device workspace (>= workspace_bytes, 256-byte
+ * aligned) and the HIP stream (hipStream_t, NULL = default stream).  Uploads
+ * the problem tables (stream-ordered).  Errors: AT_EINVAL, AT_EHIP. */
+int at_bind(at_ctx* ctx, void* d_workspace, size_t bytes, void* hip_stream);
+
+/* Set problem `prob`'s level-0 state: F x N doubles (structure of arrays,
+ * field-major) on the host (q_on_device = 0; copied before return) or on the
+ * device (stream-ordered).  Resets the step counter of the context to 0 when
+ * called before the first step; AT_ESTATE after stepping (use at_reset). */
+int at_set_state(at_ctx* ctx, int prob, const double* q, int q_on_device);
+
+/* Forget all progress: step counter and stage pointer to 0; states must be set again. */
+int at_reset(at_ctx* ctx);
+
+/* One RK stage (1-based, 1..S) of the current step for every problem: draws
+ * the delays and builds the level's halo strips at stage 1, keeps stage
+ * right-hand sides in the workspace, and at stage S forms u^{n+1} and
+ * advances the step.  Stages must be called in order.  Needs stage_api.
+ * Results equal at_step's.  Errors: AT_ESTATE, AT_EINVAL, AT_EHIP. */
+int at_rk_stage(at_ctx* ctx, int stage);
+
+/* Plain form: n_steps steps, each one fused all-stage kernel launch per problem. */
+int at_step(at_ctx* ctx, int n_steps);
+
+/* Batched form: n_steps steps, each one launch per kernel variant over the
+ * work list of all problems (persistent or one workgroup per tile), replayed
+ * from captured HIP graphs of graph_steps steps when enabled. */
+int at_batch_step(at_ctx* ctx, int n_steps);
+
+/* Copy problem `prob`'s current state out as F x N doubles (hi + lo for the
+ * FP32 forms).  out_on_device = 0: host buffer, synchronises the stream. */
+int at_get_state(at_ctx* ctx, int prob, double* out, int out_on_device);
+
+/* Delays drawn and used (effective, clamped to the held history) for steps
+ * [step0, step0 + n_steps), each P x 2 (PE, side) bytes; needs log_steps and
+ * the steps to be inside the logged window.  Synchronises the stream. */
+int at_get_delays(at_ctx* ctx, int prob, int64_t step0, int n_steps, uint8_t* drawn,
+                  uint8_t* effective);
+
+/* Replace the drawn delays of problem `prob` for steps [step0, step0+n_steps)
+ * by sched (n_steps x P x 2 bytes, host).  Values above kmax: AT_ESTALE (the
+ * ring holds only kmax + J levels).  n_steps = 0 clears.  Needs override_steps. */
+int at_set_delay_override(at_ctx* ctx, int prob, const uint8_t* sched, int64_t step0,
+                          int n_steps);
+
+/* Wait for the context's stream. */
+int at_sync(at_ctx* ctx);
+
+/* Introspection: AT_Q_* keys below; value out.  Errors: AT_EINVAL. */
+enum at_query_key {
+    AT_Q_STEP = 0,            /* current step n                                     */
+    AT_Q_NUM_TILES = 1,       /* work items over all problems                        */
+    AT_Q_NUM_GROUPS = 2,      /* kernel variants (launches per batched step)         */
+    AT_Q_TOTAL_POINTS = 3,    /* sum of N                                            */
+    AT_Q_STATE_BYTES = 4,     /* algorithmic state bytes moved per step (read+write) */
+    AT_Q_STAGES = 5,          /* RK stages of problem 0                              */
+    AT_Q_LDS_BYTES = 6,       /* largest dynamic LDS of a launch                     */
+    AT_Q_STRIP_BYTES = 7,     /* ring strip bytes written per step                   */
+    AT_Q_NUM_PES = 8          /* sum of P                                            */
+};
+int at_query(const at_ctx* ctx, int key, int64_t* value);
+
+/* Device stream the last launches went to (for event timing on that stream). */
+void* at_stream(const at_ctx* ctx);
+
+const char* at_strerror(int code);
+const char* at_last_error(const at_ctx* ctx);
+void at_free(at_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* AT_H */

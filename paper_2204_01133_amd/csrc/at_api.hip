@@ -1,0 +1,454 @@
+// at_api.hip -- libat's C ABI (include/at.h) on HIP: planning, the caller-owned
+// workspace, state conversion kernels, the plain / batched / per-stage step
+// launches and HIP-graph replay of batched steps.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/at.h"
+#include "at_kernels.hpp"
+#include "at_plan.hpp"
+
+using namespace atk;
+
+struct at_ctx {
+    Plan plan;
+    std::string err;
+    unsigned char* ws = nullptr;
+    size_t ws_bytes = 0;
+    hipStream_t stream = nullptr;
+    bool bound = false;
+    int64_t step = 0;
+    int stage = 0;
+    std::vector<uint8_t> state_set;
+    std::vector<int64_t> ov_step0, ov_n;
+    std::vector<ProbDev> pd;
+    int num_cus = 256;
+    // graph of graph_steps batched steps
+    hipGraphExec_t gexec = nullptr;
+    hipGraph_t graph = nullptr;
+    int graph_len = 0;
+};
+
+namespace {
+
+int fail(at_ctx* c, int code, const std::string& msg) {
+    if (c) c->err = msg;
+    return code;
+}
+
+int hip_fail(at_ctx* c, hipError_t e, const char* where) {
+    return fail(c, AT_EHIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define HIPCHK(c, expr)                                          \
+    do {                                                         \
+        hipError_t _e = (expr);                                  \
+        if (_e != hipSuccess) return hip_fail((c), _e, #expr);   \
+    } while (0)
+
+__global__ void k_split(const double* __restrict__ q, float* __restrict__ hi, float* __restrict__ lo,
+                        int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double v = q[i];
+    const float h = (float)v;
+    hi[i] = h;
+    if (lo) lo[i] = (float)(v - (double)h);
+}
+
+__global__ void k_join(const float* __restrict__ hi, const float* __restrict__ lo, double* __restrict__ out,
+                       int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    out[i] = (double)hi[i] + (lo ? (double)lo[i] : 0.0);
+}
+
+__global__ void k_set_step(int64_t* d, int64_t v) { *d = v; }
+__global__ void k_add_step(int64_t* d, int64_t v) { *d += v; }
+
+int launch_key(at_ctx* c, const VariantKey& k, const KArgs& a, int grid) {
+    if (grid <= 0 || a.ntiles <= 0) return AT_OK;
+    hipError_t e = hipSuccess;
+    bool ok = launch_adr(k, a, grid, c->stream, &e) || launch_rns(k, a, grid, c->stream, &e) ||
+              launch_wscal(k, a, grid, c->stream, &e) || launch_eul(k, a, grid, c->stream, &e) ||
+              launch_reul(k, a, grid, c->stream, &e);
+    if (!ok) return fail(c, AT_EUNSUPPORTED, "kernel variant not compiled");
+    if (e != hipSuccess) return hip_fail(c, e, "tile kernel launch");
+    return AT_OK;
+}
+
+KArgs base_args(at_ctx* c, const Group& g) {
+    KArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.probs = (const ProbDev*)(c->ws + c->plan.off_probs);
+    a.npts_max = g.npts_max;
+    a.npe_max = g.npe_max;
+    a.jmax = g.jmax;
+    a.lds_bytes = (int32_t)g.lds_bytes;
+    a.flags = (c->plan.opts.log_steps ? KF_LOG : 0) | (c->plan.opts.xcd_remap ? KF_XCD : 0);
+    return a;
+}
+
+int upload_probs(at_ctx* c) {
+    for (size_t b = 0; b < c->plan.desc.size(); ++b)
+        fill_probdev(c->plan, (int)b, c->ws, c->pd[b], c->ov_step0[b], c->ov_n[b]);
+    HIPCHK(c, hipMemcpyAsync(c->ws + c->plan.off_probs, c->pd.data(), sizeof(ProbDev) * c->pd.size(),
+                             hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return AT_OK;
+}
+
+int check_ready(at_ctx* c) {
+    if (!c) return AT_EINVAL;
+    if (!c->bound) return fail(c, AT_ESTATE, "workspace not bound");
+    for (size_t b = 0; b < c->state_set.size(); ++b)
+        if (!c->state_set[b]) return fail(c, AT_ESTATE, "state of a problem not set");
+    return AT_OK;
+}
+
+// one batched step (all groups, all stages) with step counter n or from the device counter
+int batched_step_launches(at_ctx* c, const int64_t* step_ptr, int64_t step_off) {
+    for (const Group& g : c->plan.groups) {
+        KArgs a = base_args(c, g);
+        a.tiles = (const Tile*)(c->ws + c->plan.off_tiles_bt) + g.t0;
+        a.ntiles = g.ntiles;
+        a.step_ptr = step_ptr;
+        a.step_off = step_off;
+        a.s_begin = 0;
+        a.s_end = g.key.S - 1;
+        int persistent = c->plan.opts.persistent;
+        if (persistent < 0) persistent = g.ntiles > 8 * c->num_cus ? 1 : 0;
+        const int per_cu = c->plan.opts.grid_per_cu > 0 ? c->plan.opts.grid_per_cu : 4;
+        const int grid = persistent ? std::min(g.ntiles, per_cu * c->num_cus) : g.ntiles;
+        int rc = launch_key(c, g.key, a, grid);
+        if (rc) return rc;
+    }
+    return AT_OK;
+}
+
+void drop_graph(at_ctx* c) {
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    c->gexec = nullptr;
+    c->graph = nullptr;
+    c->graph_len = 0;
+}
+
+int build_graph(at_ctx* c, int len) {
+    drop_graph(c);
+    int64_t* d_step = (int64_t*)(c->ws + c->plan.off_step);
+    HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    int rc = AT_OK;
+    for (int k = 0; k < len && rc == AT_OK; ++k) rc = batched_step_launches(c, d_step, k);
+    if (rc == AT_OK) hipLaunchKernelGGL(k_add_step, dim3(1), dim3(1), 0, c->stream, d_step, (int64_t)len);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(c->stream, &g);
+    if (rc) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess) return hip_fail(c, e, "hipStreamEndCapture");
+    c->graph = g;
+    e = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        drop_graph(c);
+        return hip_fail(c, e, "hipGraphInstantiate");
+    }
+    c->graph_len = len;
+    return AT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int at_init(const at_problem_desc* probs, int n_probs, const at_run_opts* opts, at_ctx** out,
+            size_t* workspace_bytes) {
+    if (!out || !workspace_bytes) return AT_EINVAL;
+    *out = nullptr;
+    at_ctx* c = new at_ctx();
+    int rc = make_plan(probs, n_probs, opts, c->plan, c->err);
+    if (rc) {
+        fprintf(stderr, "at_init: %s\n", c->err.c_str());
+        delete c;
+        return rc;
+    }
+    c->state_set.assign(n_probs, 0);
+    c->ov_step0.assign(n_probs, 0);
+    c->ov_n.assign(n_probs, 0);
+    c->pd.resize(n_probs);
+    int dev = 0;
+    if (hipGetDevice(&dev) == hipSuccess) {
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+            c->num_cus = cus;
+    }
+    *workspace_bytes = c->plan.total;
+    *out = c;
+    return AT_OK;
+}
+
+int at_bind(at_ctx* c, void* d_workspace, size_t bytes, void* hip_stream) {
+    if (!c || !d_workspace) return AT_EINVAL;
+    if (bytes < c->plan.total) return fail(c, AT_EINVAL, "workspace too small");
+    if (((uintptr_t)d_workspace & 255) != 0) return fail(c, AT_EINVAL, "workspace not 256-byte aligned");
+    drop_graph(c);
+    c->ws = (unsigned char*)d_workspace;
+    c->ws_bytes = bytes;
+    c->stream = (hipStream_t)hip_stream;
+    HIPCHK(c, hipMemcpyAsync(c->ws + c->plan.off_tiles_pm, c->plan.tiles_pm.data(),
+                             sizeof(Tile) * c->plan.tiles_pm.size(), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->ws + c->plan.off_tiles_bt, c->plan.tiles_bt.data(),
+                             sizeof(Tile) * c->plan.tiles_bt.size(), hipMemcpyHostToDevice, c->stream));
+    c->bound = true;
+    return upload_probs(c);
+}
+
+int at_reset(at_ctx* c) {
+    if (!c) return AT_EINVAL;
+    c->step = 0;
+    c->stage = 0;
+    std::fill(c->state_set.begin(), c->state_set.end(), 0);
+    return AT_OK;
+}
+
+int at_set_state(at_ctx* c, int prob, const double* q, int q_on_device) {
+    if (!c || !q) return AT_EINVAL;
+    if (!c->bound) return fail(c, AT_ESTATE, "workspace not bound");
+    if (prob < 0 || prob >= (int)c->plan.desc.size()) return fail(c, AT_EINVAL, "problem index");
+    if (c->step != 0 || c->stage != 0) return fail(c, AT_ESTATE, "state set after stepping (at_reset first)");
+    const ProbInfo& pi = c->plan.info[prob];
+    const int prec = c->plan.desc[prob].precision;
+    const int64_t n = pi.st_elems;
+    if (prec == AT_FP64) {
+        HIPCHK(c, hipMemcpyAsync(c->ws + pi.off_hi[0], q, 8 * (size_t)n,
+                                 q_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->stream));
+        if (!q_on_device) HIPCHK(c, hipStreamSynchronize(c->stream));
+    } else if (q_on_device) {
+        float* lo = prec == AT_FP32C ? (float*)(c->ws + pi.off_lo[0]) : nullptr;
+        hipLaunchKernelGGL(k_split, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, q,
+                           (float*)(c->ws + pi.off_hi[0]), lo, n);
+        HIPCHK(c, hipGetLastError());
+    } else {
+        std::vector<float> hi(n), lo(n);
+        for (int64_t i = 0; i < n; ++i) {
+            hi[i] = (float)q[i];
+            lo[i] = (float)(q[i] - (double)hi[i]);
+        }
+        HIPCHK(c, hipMemcpyAsync(c->ws + pi.off_hi[0], hi.data(), 4 * (size_t)n, hipMemcpyHostToDevice, c->stream));
+        if (prec == AT_FP32C)
+            HIPCHK(c, hipMemcpyAsync(c->ws + pi.off_lo[0], lo.data(), 4 * (size_t)n, hipMemcpyHostToDevice,
+                                     c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
+    c->state_set[prob] = 1;
+    return AT_OK;
+}
+
+int at_step(at_ctx* c, int n_steps) {
+    int rc = check_ready(c);
+    if (rc) return rc;
+    if (c->stage != 0) return fail(c, AT_ESTATE, "at_step inside a per-stage step");
+    if (n_steps < 0) return fail(c, AT_EINVAL, "negative step count");
+    for (int i = 0; i < n_steps; ++i) {
+        for (size_t b = 0; b < c->plan.desc.size(); ++b) {
+            const ProbInfo& pi = c->plan.info[b];
+            const Group& g = c->plan.groups[pi.group];
+            KArgs a = base_args(c, g);
+            a.tiles = (const Tile*)(c->ws + c->plan.off_tiles_pm) + pi.t0;
+            a.ntiles = pi.ntiles;
+            a.step_off = c->step;
+            a.s_begin = 0;
+            a.s_end = pi.S - 1;
+            rc = launch_key(c, pi.key, a, pi.ntiles);
+            if (rc) return rc;
+        }
+        c->step += 1;
+    }
+    return AT_OK;
+}
+
+int at_batch_step(at_ctx* c, int n_steps) {
+    int rc = check_ready(c);
+    if (rc) return rc;
+    if (c->stage != 0) return fail(c, AT_ESTATE, "at_batch_step inside a per-stage step");
+    if (n_steps < 0) return fail(c, AT_EINVAL, "negative step count");
+    const int gl = c->plan.opts.graph_steps;
+    int done = 0;
+    if (gl > 0 && c->stream != nullptr && n_steps >= gl) {
+        if (!c->gexec || c->graph_len != gl) {
+            rc = build_graph(c, gl);
+            if (rc) return rc;
+        }
+        int64_t* d_step = (int64_t*)(c->ws + c->plan.off_step);
+        hipLaunchKernelGGL(k_set_step, dim3(1), dim3(1), 0, c->stream, d_step, c->step);
+        HIPCHK(c, hipGetLastError());
+        while (n_steps - done >= gl) {
+            HIPCHK(c, hipGraphLaunch(c->gexec, c->stream));
+            done += gl;
+            c->step += gl;
+        }
+    }
+    for (; done < n_steps; ++done) {
+        rc = batched_step_launches(c, nullptr, c->step);
+        if (rc) return rc;
+        c->step += 1;
+    }
+    return AT_OK;
+}
+
+int at_rk_stage(at_ctx* c, int stage) {
+    int rc = check_ready(c);
+    if (rc) return rc;
+    if (!c->plan.opts.stage_api) return fail(c, AT_ESTATE, "stage buffers not reserved (stage_api)");
+    const int S = c->plan.info[0].S;
+    for (const ProbInfo& pi : c->plan.info)
+        if (pi.S != S) return fail(c, AT_EUNSUPPORTED, "per-stage stepping needs one RK scheme");
+    if (stage != c->stage + 1 || stage < 1 || stage > S)
+        return fail(c, AT_ESTATE, "stages must be called in order 1..S");
+    for (const Group& g : c->plan.groups) {
+        KArgs a = base_args(c, g);
+        a.tiles = (const Tile*)(c->ws + c->plan.off_tiles_bt) + g.t0;
+        a.ntiles = g.ntiles;
+        a.step_off = c->step;
+        a.s_begin = stage - 1;
+        a.s_end = stage - 1;
+        a.flags |= KF_STAGE_IO;
+        rc = launch_key(c, g.key, a, g.ntiles);
+        if (rc) return rc;
+    }
+    c->stage = stage;
+    if (stage == S) {
+        c->stage = 0;
+        c->step += 1;
+    }
+    return AT_OK;
+}
+
+int at_get_state(at_ctx* c, int prob, double* out, int out_on_device) {
+    if (!c || !out) return AT_EINVAL;
+    if (!c->bound) return fail(c, AT_ESTATE, "workspace not bound");
+    if (prob < 0 || prob >= (int)c->plan.desc.size()) return fail(c, AT_EINVAL, "problem index");
+    const ProbInfo& pi = c->plan.info[prob];
+    const int prec = c->plan.desc[prob].precision;
+    const int w = (int)(c->step & 1);
+    const int64_t n = pi.st_elems;
+    if (prec == AT_FP64) {
+        HIPCHK(c, hipMemcpyAsync(out, c->ws + pi.off_hi[w], 8 * (size_t)n,
+                                 out_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream));
+    } else if (out_on_device) {
+        const float* lo = prec == AT_FP32C ? (const float*)(c->ws + pi.off_lo[w]) : nullptr;
+        hipLaunchKernelGGL(k_join, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream,
+                           (const float*)(c->ws + pi.off_hi[w]), lo, out, n);
+        HIPCHK(c, hipGetLastError());
+    } else {
+        std::vector<float> hi(n), lo(n, 0.f);
+        HIPCHK(c, hipMemcpyAsync(hi.data(), c->ws + pi.off_hi[w], 4 * (size_t)n, hipMemcpyDeviceToHost, c->stream));
+        if (prec == AT_FP32C)
+            HIPCHK(c, hipMemcpyAsync(lo.data(), c->ws + pi.off_lo[w], 4 * (size_t)n, hipMemcpyDeviceToHost,
+                                     c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        for (int64_t i = 0; i < n; ++i) out[i] = (double)hi[i] + (double)lo[i];
+        return AT_OK;
+    }
+    if (!out_on_device) HIPCHK(c, hipStreamSynchronize(c->stream));
+    return AT_OK;
+}
+
+int at_get_delays(at_ctx* c, int prob, int64_t step0, int n_steps, uint8_t* drawn, uint8_t* eff) {
+    if (!c || !drawn || !eff) return AT_EINVAL;
+    if (!c->bound) return fail(c, AT_ESTATE, "workspace not bound");
+    if (prob < 0 || prob >= (int)c->plan.desc.size()) return fail(c, AT_EINVAL, "problem index");
+    const int64_t cap = c->plan.opts.log_steps;
+    if (cap == 0) return fail(c, AT_EINVAL, "delay log disabled (log_steps = 0)");
+    if (n_steps < 0 || step0 < 0 || step0 + n_steps > c->step || step0 < c->step - cap)
+        return fail(c, AT_ERANGE, "steps outside the logged window");
+    const ProbInfo& pi = c->plan.info[prob];
+    const int64_t P = c->plan.desc[prob].p;
+    for (int i = 0; i < n_steps; ++i) {
+        const int64_t slot = (step0 + i) % cap;
+        HIPCHK(c, hipMemcpyAsync(drawn + (int64_t)i * P * 2, c->ws + pi.off_log_d + slot * P * 2, (size_t)P * 2,
+                                 hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipMemcpyAsync(eff + (int64_t)i * P * 2, c->ws + pi.off_log_e + slot * P * 2, (size_t)P * 2,
+                                 hipMemcpyDeviceToHost, c->stream));
+    }
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return AT_OK;
+}
+
+int at_set_delay_override(at_ctx* c, int prob, const uint8_t* sched, int64_t step0, int n_steps) {
+    if (!c) return AT_EINVAL;
+    if (!c->bound) return fail(c, AT_ESTATE, "workspace not bound");
+    if (prob < 0 || prob >= (int)c->plan.desc.size()) return fail(c, AT_EINVAL, "problem index");
+    if (n_steps < 0 || step0 < 0) return fail(c, AT_EINVAL, "negative step");
+    if (n_steps > c->plan.opts.override_steps) return fail(c, AT_EINVAL, "schedule longer than override_steps");
+    if (n_steps > 0 && !sched) return AT_EINVAL;
+    const int64_t P = c->plan.desc[prob].p;
+    for (int64_t i = 0; i < (int64_t)n_steps * P * 2; ++i)
+        if (sched[i] > c->plan.desc[prob].kmax)
+            return fail(c, AT_ESTALE, "override delay above kmax: the ring holds kmax + J levels");
+    if (n_steps > 0) {
+        HIPCHK(c, hipMemcpyAsync(c->ws + c->plan.info[prob].off_ov, sched, (size_t)n_steps * P * 2,
+                                 hipMemcpyHostToDevice, c->stream));
+    }
+    c->ov_step0[prob] = step0;
+    c->ov_n[prob] = n_steps;
+    return upload_probs(c);
+}
+
+int at_sync(at_ctx* c) {
+    if (!c) return AT_EINVAL;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return AT_OK;
+}
+
+int at_query(const at_ctx* c, int key, int64_t* v) {
+    if (!c || !v) return AT_EINVAL;
+    switch (key) {
+    case AT_Q_STEP: *v = c->step; return AT_OK;
+    case AT_Q_NUM_TILES: *v = (int64_t)c->plan.tiles_bt.size(); return AT_OK;
+    case AT_Q_NUM_GROUPS: *v = (int64_t)c->plan.groups.size(); return AT_OK;
+    case AT_Q_TOTAL_POINTS: *v = c->plan.total_points; return AT_OK;
+    case AT_Q_STATE_BYTES: *v = c->plan.state_bytes_per_step; return AT_OK;
+    case AT_Q_STAGES: *v = c->plan.info[0].S; return AT_OK;
+    case AT_Q_LDS_BYTES: {
+        int64_t m = 0;
+        for (const Group& g : c->plan.groups) m = std::max(m, g.lds_bytes);
+        *v = m;
+        return AT_OK;
+    }
+    case AT_Q_STRIP_BYTES: *v = c->plan.strip_bytes_per_step; return AT_OK;
+    case AT_Q_NUM_PES: *v = c->plan.total_pes; return AT_OK;
+    }
+    return AT_EINVAL;
+}
+
+void* at_stream(const at_ctx* c) { return c ? (void*)c->stream : nullptr; }
+
+const char* at_strerror(int code) {
+    switch (code) {
+    case AT_OK: return "ok";
+    case AT_EINVAL: return "invalid argument";
+    case AT_EUNSUPPORTED: return "unsupported";
+    case AT_ESTATE: return "wrong call order";
+    case AT_EHIP: return "HIP error";
+    case AT_ESTALE: return "delay older than the ring holds";
+    case AT_ERANGE: return "out of range";
+    }
+    return "unknown error";
+}
+
+const char* at_last_error(const at_ctx* c) { return c ? c->err.c_str() : "no context"; }
+
+void at_free(at_ctx* c) {
+    if (!c) return;
+    drop_graph(c);
+    delete c;
+}
+
+}  // extern "C"

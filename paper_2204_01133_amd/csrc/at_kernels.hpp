@@ -1,0 +1,77 @@
+// at_kernels.hpp -- gfx950 tile kernels: one workgroup of 256 threads runs the
+// tile step of at_tile.hpp for one work item (non-persistent) or strides over
+// the work list (persistent).  Own-point state and the S stage right-hand sides
+// live in registers, tile data in dynamic LDS.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "at_plan.hpp"
+#include "at_variants.hpp"
+
+namespace atk {
+
+template <class C>
+struct GpuRT {
+    TS<C> ts;
+    __device__ int nthreads() const { return (int)blockDim.x; }
+    template <class Fn>
+    __device__ void each(Fn&& f) { f((int)threadIdx.x, ts); }
+    __device__ void sync() { __syncthreads(); }
+};
+
+// Work item order with consecutive items on one XCD: workgroup i runs on XCD
+// i mod 8, so item = (first item of that XCD's share) + i / 8.
+__device__ __forceinline__ int xcd_item(int it, int n) {
+    const int q = n >> 3, r = n & 7, x = it & 7, j = it >> 3;
+    return x * q + (x < r ? x : r) + j;
+}
+
+template <class C>
+__global__ __launch_bounds__(BLOCK) void at_tile_kernel(KArgs a) {
+    extern __shared__ __align__(16) unsigned char lds[];
+    GpuRT<C> rt;
+    const int64_t n = (a.step_ptr ? *a.step_ptr : 0) + a.step_off;
+    const bool remap = (a.flags & KF_XCD) && (int)gridDim.x == a.ntiles;
+    for (int it = blockIdx.x; it < a.ntiles; it += gridDim.x) {
+        const int ti = remap ? xcd_item(it, a.ntiles) : it;
+        const Tile t = a.tiles[ti];
+        tile_step<C>(rt, a, t, a.probs[t.prob], n, lds);
+        __syncthreads();
+    }
+}
+
+template <class C>
+hipError_t launch_variant(const KArgs& a, int grid, hipStream_t s) {
+    static bool attr_done = false;
+    if (!attr_done) {
+        hipError_t e = hipFuncSetAttribute((const void*)at_tile_kernel<C>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        if (e != hipSuccess) return e;
+        attr_done = true;
+    }
+    hipLaunchKernelGGL(at_tile_kernel<C>, dim3(grid), dim3(BLOCK), (size_t)a.lds_bytes, s, a);
+    return hipGetLastError();
+}
+
+// per-kind dispatchers (one translation unit each); return false if the key is not theirs
+bool launch_adr(const VariantKey& k, const KArgs& a, int grid, hipStream_t s, hipError_t* e);
+bool launch_rns(const VariantKey& k, const KArgs& a, int grid, hipStream_t s, hipError_t* e);
+bool launch_wscal(const VariantKey& k, const KArgs& a, int grid, hipStream_t s, hipError_t* e);
+bool launch_eul(const VariantKey& k, const KArgs& a, int grid, hipStream_t s, hipError_t* e);
+bool launch_reul(const VariantKey& k, const KArgs& a, int grid, hipStream_t s, hipError_t* e);
+
+}  // namespace atk
+
+#define AT_LAUNCH_CASE(K, H_, S_, F32_)                                               \
+    if (k.kind == (K) && k.H == (H_) && k.S == (S_) && k.f32 == ((F32_) != 0)) {      \
+        *e = launch_variant<AT_CFG(K, H_, S_, F32_)>(a, grid, s);                     \
+        return true;                                                                  \
+    }
+
+#define AT_DEFINE_LAUNCHER(NAME, LIST)                                                           \
+    namespace atk {                                                                              \
+    bool NAME(const VariantKey& k, const KArgs& a, int grid, hipStream_t s, hipError_t* e) {     \
+        LIST(AT_LAUNCH_CASE)                                                                     \
+        return false;                                                                            \
+    }                                                                                            \
+    }

@@ -1,0 +1,954 @@
+// at_tile.hpp -- the work of one tile (a run of whole PEs of one problem) for
+// one asynchrony-tolerant RK step, written once for the gfx950 kernels and for
+// the bounds-checked CPU emulation used by the tests.
+//
+// Method (Kumari et al., arXiv:2204.01133):
+//   * delays: one draw per PE / PE side / boundary and step from a counter-based
+//     hash (SplitMix64 finaliser), uniform or by cumulative thresholds
+//     (Sec. 2.1; Sec. 5, Table dels);
+//   * multi-stage AT procedure (Sec. 2.3): the halo value of stage s at a
+//     delayed level m is the synchronous stage s of the global level m; it is
+//     computed once, when level m is current, from a window of 2*S*H raw
+//     points around each PE boundary, and kept in a ring of per-PE "strips"
+//     (S stages x H points x F fields per side) in HBM;
+//   * AT halo: Lagrange extrapolation in time of the differentiated quantity
+//     from levels n-k, ..., n-k-J+1 to level n with exact integer weights
+//     (Table A for J = 3; eqs. atRecon, beta2AT* for J = 2);
+//   * interior: central differences of order 2H (Table A's 4th order, 2nd
+//     order of eq. at1, 8th order) or WENO5-JS with local Lax-Friedrichs
+//     splitting (eqs. Csplit, wender, omg, betaS, idRec);
+//   * RK stages in Butcher form (eq. rk1), all stages of a step fused.
+//
+// Data layout in LDS ("ext" positions): per PE of the tile H halo slots, its own
+// points, H halo slots (concatenated); then one window of 2*S*H positions per
+// PE boundary.  Own-point state and stage right-hand sides stay in registers.
+#pragma once
+#include <math.h>
+#include <stdint.h>
+
+#include <type_traits>
+
+#ifdef __HIPCC__
+#define AT_HD __host__ __device__
+#define AT_FI __forceinline__
+#else
+#define AT_HD
+#define AT_FI inline
+#endif
+
+#ifdef AT_EMU
+void at_emu_fail(const char* what, const char* file, int line, long long i, long long n);
+#define AT_CHECK(c, what, i, n) \
+    do { if (!(c)) at_emu_fail(what, __FILE__, __LINE__, (long long)(i), (long long)(n)); } while (0)
+#else
+#define AT_CHECK(c, what, i, n) ((void)0)
+#endif
+
+namespace atk {
+
+enum Kind { K_ADR = 0, K_RNS = 1, K_WSCAL = 2, K_EUL = 3, K_REUL = 4 };
+enum Pde { PDE_ADV_DIFF = 0, PDE_ADR_LOGISTIC = 1, PDE_BURGERS = 2, PDE_EULER = 3,
+           PDE_REACTIVE_EULER = 4, PDE_REACTIVE_NS = 5 };
+enum Mode { M_SYNC = 0, M_AS = 1, M_AT = 2 };
+enum Gran { G_PE = 0, G_PE_SIDE = 1, G_BOUNDARY = 2 };
+
+constexpr int MAXF = 4;
+constexpr int MAXS = 4;
+constexpr int MAXJ = 8;
+
+// Bounds-checked in the CPU emulation, a plain pointer on the GPU.
+template <class T>
+struct View {
+    T* p;
+    int64_t n;
+    AT_HD AT_FI T& operator[](int64_t i) const {
+        AT_CHECK(i >= 0 && i < n, "view", i, n);
+        return p[i];
+    }
+};
+
+// Device-resident description of one problem (built by the planner).
+struct ProbDev {
+    int64_t n;
+    int32_t p, pde, mode, gran, kmax, J, D, n_cdf, keep_lo, S, F;
+    uint64_t cdf[16];
+    uint64_t seed;
+    int64_t pid;
+    double dt, inv_dx, inv_dx2;
+    double c, alpha, r, gamma, q, ea, b, mu, kappa, rhoD, eps;
+    double a[MAXS][MAXS];
+    double bw[MAXS];
+    // memory (device addresses; host addresses in the emulation)
+    void* st_hi[2];          // state ping-pong: F x N (FP64 value or FP32 hi)
+    void* st_lo[2];          // FP32 forms: lo parts
+    void* ring;              // strip ring: D x P x 2 records of rec_bytes
+    int64_t rec_bytes;
+    void* kbuf;              // stage right-hand sides for the per-stage entry point
+    uint8_t* ov;             // delay override [ov_n][P][2]
+    int64_t ov_step0, ov_n;
+    uint8_t* log_drawn;      // delay log ring [log_cap][P][2]
+    uint8_t* log_eff;
+    int64_t log_cap;
+    int64_t kbuf_len;        // elements (emulation bounds)
+};
+
+struct Tile {
+    int32_t prob, pe0, npe, npts;
+    int64_t lo;              // first global point of the tile
+};
+
+enum KFlags { KF_STAGE_IO = 1, KF_LOG = 2, KF_XCD = 4 };
+
+struct KArgs {
+    const Tile* tiles;
+    const ProbDev* probs;
+    const int64_t* step_ptr;  // device step counter (graph replays), may be null
+    int64_t step_off;
+    int32_t ntiles, npts_max, npe_max, jmax;
+    int32_t s_begin, s_end, flags, lds_bytes;
+};
+
+// ---------------------------------------------------------------------------
+// kind traits and configuration
+// ---------------------------------------------------------------------------
+template <int KIND> struct KindInfo;
+template <> struct KindInfo<K_ADR>   { static constexpr int F = 1, NQ = 1; static constexpr bool WENO = false, T64 = false; };
+template <> struct KindInfo<K_RNS>   { static constexpr int F = 4, NQ = 7; static constexpr bool WENO = false, T64 = true; };
+template <> struct KindInfo<K_WSCAL> { static constexpr int F = 1, NQ = 2; static constexpr bool WENO = true, T64 = false; };
+template <> struct KindInfo<K_EUL>   { static constexpr int F = 3, NQ = 6; static constexpr bool WENO = true, T64 = false; };
+template <> struct KindInfo<K_REUL>  { static constexpr int F = 4, NQ = 8; static constexpr bool WENO = true, T64 = true; };
+
+template <int KIND_, int H_, int S_, bool F32_, int PPT_>
+struct Cfg {
+    static constexpr int KIND = KIND_, H = H_, S = S_, PPT = PPT_;
+    static constexpr bool F32 = F32_;
+    using KI = KindInfo<KIND_>;
+    static constexpr int F = KI::F, NQ = KI::NQ;
+    static constexpr bool WENO = KI::WENO;
+    static constexpr bool HILO = F32_ && KIND_ == K_ADR;        // hi/lo difference stencils
+    using lreal = typename std::conditional<F32_, float, double>::type;   // LDS values, K
+    using qreal = typename std::conditional<F32_ && !KI::T64, float, double>::type;  // quantities
+    static constexpr int WL = 2 * S_ * H_;                      // boundary window length
+};
+
+AT_HD AT_FI int64_t align16(int64_t b) { return (b + 15) & ~int64_t(15); }
+
+// LDS layout of a launch (same function on host and device).
+template <class C>
+struct Layout {
+    int64_t EXM, EXW, EX, NW, SOREC;
+    int64_t o_g, o_glo, o_lam, o_flux, o_wu, o_wulo, o_wq, o_wR, o_SN, o_SNhi, o_SO, o_SOhi,
+        o_pelo, o_keff, total;
+    AT_HD void init(int npts_max, int npe_max, int jmax) {
+        using L = typename C::lreal;
+        const int64_t sl = (int64_t)sizeof(L);
+        EXM = npts_max + 2 * C::H * (int64_t)npe_max;
+        NW = npe_max + 1;
+        EXW = NW * C::WL;
+        EX = EXM + EXW;
+        SOREC = (int64_t)jmax * C::S * C::H * C::F;  // per PE side
+        int64_t o = 0;
+        o_g = o;    o += align16(C::NQ * EX * sl);
+        o_glo = o;  o += C::HILO ? align16(EX * 4) : 0;
+        o_lam = o;  o += C::WENO ? align16(EX * sl) : 0;
+        o_flux = o; o += C::WENO ? align16(C::F * EX * sl) : 0;
+        o_wu = o;   o += align16(C::F * EXW * sl);
+        o_wulo = o; o += C::F32 ? align16(C::F * EXW * 4) : 0;
+        o_wq = o;   o += align16(C::F * EXW * sl);
+        o_wR = o;   o += align16((C::S > 1 ? C::S - 1 : 1) * C::F * EXW * sl);
+        o_SN = o;   o += align16(NW * C::S * 2 * C::H * C::F * sl);
+        o_SNhi = o; o += C::F32 ? align16(NW * 2 * C::H * C::F * 4) : 0;
+        o_SO = o;   o += align16(2 * (int64_t)npe_max * SOREC * sl);
+        o_SOhi = o; o += C::F32 ? align16(2 * (int64_t)npe_max * jmax * C::H * C::F * 4) : 0;
+        o_pelo = o; o += align16((npe_max + 1) * 4);
+        o_keff = o; o += align16(2 * (int64_t)npe_max * 4);
+        total = o;
+    }
+};
+
+// strip record: FP64: G[s][h][f] doubles; FP32 forms: hi[h][f] floats then lo[s][h][f]
+template <class C>
+AT_HD AT_FI int64_t record_bytes() {
+    return C::F32 ? (int64_t)(C::H * C::F + C::S * C::H * C::F) * 4
+                  : (int64_t)C::S * C::H * C::F * 8;
+}
+
+// ---------------------------------------------------------------------------
+// delays: SplitMix64 finaliser as a counter-based hash
+// ---------------------------------------------------------------------------
+AT_HD AT_FI uint64_t mix64(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
+    return z ^ (z >> 31);
+}
+
+AT_HD AT_FI int draw_delay(const ProbDev& P, int64_t step, int64_t idx, int side) {
+    const uint64_t g = 0x9e3779b97f4a7c15ULL;
+    uint64_t z = mix64(P.seed + g * (uint64_t)(P.pid + 1));
+    z = mix64(z + g * (uint64_t)(step + 1));
+    z = mix64(z + g * (uint64_t)(2 * idx + side + 1));
+    const uint64_t top = z >> 32;
+    if (P.n_cdf == 0) return (int)((top * (uint64_t)(P.kmax + 1)) >> 32);
+    int k = 0;
+    while (k < P.kmax && top >= P.cdf[k]) ++k;
+    return k;
+}
+
+// Lagrange weights from levels -k..-k-J+1 to 0: w_l = prod_{m!=l} (k+m)/(m-l), exact integers.
+AT_HD AT_FI void lagrange_weights(int J, int k, double* w) {
+    for (int l = 0; l < J; ++l) {
+        int64_t num = 1, den = 1;
+        for (int m = 0; m < J; ++m) {
+            if (m == l) continue;
+            num *= (int64_t)(k + m);
+            den *= (int64_t)(m - l);
+        }
+        w[l] = (double)(num / den);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// central finite-difference weights (textbook, order 2H)
+// ---------------------------------------------------------------------------
+template <int H> struct FD;
+template <> struct FD<1> {
+    AT_HD static constexpr double c1(int o) { return o == 1 ? 0.5 : 0.0; }
+    AT_HD static constexpr double c2(int o) { return o == 0 ? -2.0 : 1.0; }
+};
+template <> struct FD<2> {
+    AT_HD static constexpr double c1(int o) { return o == 1 ? 2.0 / 3.0 : -1.0 / 12.0; }
+    AT_HD static constexpr double c2(int o) { return o == 0 ? -2.5 : (o == 1 ? 4.0 / 3.0 : -1.0 / 12.0); }
+};
+template <> struct FD<4> {
+    AT_HD static constexpr double c1(int o) {
+        return o == 1 ? 0.8 : (o == 2 ? -0.2 : (o == 3 ? 4.0 / 105.0 : -1.0 / 280.0));
+    }
+    AT_HD static constexpr double c2(int o) {
+        return o == 0 ? -205.0 / 72.0 : (o == 1 ? 1.6 : (o == 2 ? -0.2 : (o == 3 ? 8.0 / 315.0 : -1.0 / 560.0)));
+    }
+};
+template <> struct FD<3> {   // unused (WENO); keeps templates well-formed
+    AT_HD static constexpr double c1(int) { return 0.0; }
+    AT_HD static constexpr double c2(int) { return 0.0; }
+};
+
+// ---------------------------------------------------------------------------
+// physics helpers
+// ---------------------------------------------------------------------------
+template <class R>
+AT_HD AT_FI R sq(R x) { return x * x; }
+
+// one-step chemistry, R = 1: T = (gamma-1)(E/rho - u^2/2 - q Y)
+AT_HD AT_FI void reactive_prims(const ProbDev& P, const double* q, double& rho, double& u, double& T,
+                                double& Y) {
+    rho = q[0];
+    u = q[1] / q[0];
+    const double E = q[2] / q[0];
+    Y = q[3] / q[0];
+    T = (P.gamma - 1.0) * (E - 0.5 * u * u - P.q * Y);
+}
+
+AT_HD AT_FI double arrhenius(const ProbDev& P, const double* q) {
+    double rho, u, T, Y;
+    reactive_prims(P, q, rho, u, T, Y);
+    return -P.b * rho * Y * exp(-P.ea / T);
+}
+
+// WENO5-JS reconstruction at the right edge of v2 (ideal weights 1/10, 3/5, 3/10),
+// nonlinear weights gamma_k/(eps+beta_k)^2 normalised, with the common
+// denominators multiplied out so that one division remains.
+template <class R>
+AT_HD AT_FI R weno5(R eps, R v0, R v1, R v2, R v3, R v4) {
+    const R sixth = R(1) / R(6);
+    const R p0 = (R(2) * v0 - R(7) * v1 + R(11) * v2) * sixth;
+    const R p1 = (-v1 + R(5) * v2 + R(2) * v3) * sixth;
+    const R p2 = (R(2) * v2 + R(5) * v3 - v4) * sixth;
+    const R t = R(13) / R(12);
+    const R b0 = t * sq(v0 - R(2) * v1 + v2) + R(0.25) * sq(v0 - R(4) * v1 + R(3) * v2);
+    const R b1 = t * sq(v1 - R(2) * v2 + v3) + R(0.25) * sq(v1 - v3);
+    const R b2 = t * sq(v2 - R(2) * v3 + v4) + R(0.25) * sq(R(3) * v2 - R(4) * v3 + v4);
+    const R d0 = sq(eps + b0), d1 = sq(eps + b1), d2 = sq(eps + b2);
+    const R w0 = R(0.1) * d1 * d2, w1 = R(0.6) * d0 * d2, w2 = R(0.3) * d0 * d1;
+    return (w0 * p0 + w1 * p1 + w2 * p2) / (w0 + w1 + w2);
+}
+
+// ---------------------------------------------------------------------------
+// per-thread state (registers on the GPU)
+// ---------------------------------------------------------------------------
+template <class C>
+struct TS {
+    int e[C::PPT];                                // ext index of the own point (-1: none)
+    int64_t x[C::PPT];                            // global point index
+    typename C::lreal uh[C::PPT][C::F];           // u^n (FP64 value / FP32 hi)
+    float ul[C::PPT][C::F];                       // FP32 lo
+    typename C::lreal K[C::S][C::PPT][C::F];      // stage right-hand sides
+};
+
+// LDS views of one launch
+template <class C>
+struct Lds {
+    using L = typename C::lreal;
+    View<L> g[C::NQ];
+    View<float> glo;
+    View<L> lam;
+    View<L> flux[C::F];
+    View<L> wu[C::F], wq[C::F];
+    View<float> wulo[C::F];
+    View<L> wR[C::S > 1 ? C::S - 1 : 1][C::F];
+    View<L> SN, SO;
+    View<float> SNhi, SOhi;
+    View<int> pelo, keff;
+    int64_t EXM, EX, EXW, SOREC;
+    int jmax;
+    AT_HD void init(unsigned char* base, const Layout<C>& Lo, int npe_max, int jm) {
+        EXM = Lo.EXM; EX = Lo.EX; EXW = Lo.EXW; SOREC = Lo.SOREC; jmax = jm;
+        for (int q = 0; q < C::NQ; ++q) g[q] = View<L>{(L*)(base + Lo.o_g) + q * EX, EX};
+        glo = View<float>{(float*)(base + Lo.o_glo), C::HILO ? EX : 0};
+        lam = View<L>{(L*)(base + Lo.o_lam), C::WENO ? EX : 0};
+        for (int f = 0; f < C::F; ++f) {
+            flux[f] = View<L>{(L*)(base + Lo.o_flux) + f * EX, C::WENO ? EX : 0};
+            wu[f] = View<L>{(L*)(base + Lo.o_wu) + f * EXW, EXW};
+            wq[f] = View<L>{(L*)(base + Lo.o_wq) + f * EXW, EXW};
+            wulo[f] = View<float>{(float*)(base + Lo.o_wulo) + f * EXW, C::F32 ? EXW : 0};
+            for (int s = 0; s < (C::S > 1 ? C::S - 1 : 1); ++s)
+                wR[s][f] = View<L>{(L*)(base + Lo.o_wR) + (s * C::F + f) * EXW, EXW};
+        }
+        SN = View<L>{(L*)(base + Lo.o_SN), Lo.NW * C::S * 2 * C::H * C::F};
+        SNhi = View<float>{(float*)(base + Lo.o_SNhi), C::F32 ? Lo.NW * 2 * C::H * C::F : 0};
+        SO = View<L>{(L*)(base + Lo.o_SO), 2 * (int64_t)npe_max * SOREC};
+        SOhi = View<float>{(float*)(base + Lo.o_SOhi), C::F32 ? 2 * (int64_t)npe_max * jm * C::H * C::F : 0};
+        pelo = View<int>{(int*)(base + Lo.o_pelo), npe_max + 1};
+        keff = View<int>{(int*)(base + Lo.o_keff), 2 * (int64_t)npe_max};
+    }
+};
+
+AT_HD AT_FI int64_t wrapi(int64_t x, int64_t n) {
+    int64_t r = x % n;
+    return r < 0 ? r + n : r;
+}
+
+// ---------------------------------------------------------------------------
+// quantities: differentiated values written at an ext position
+// ---------------------------------------------------------------------------
+// q: full state at the point (qreal).  For HILO the caller writes hi/lo itself.
+template <class C>
+AT_HD AT_FI void put_quant(const Lds<C>& L, const ProbDev& P, int64_t e, const typename C::qreal* q) {
+    using Q = typename C::qreal;
+    using LR = typename C::lreal;
+    if constexpr (C::KIND == K_ADR) {
+        L.g[0][e] = (LR)q[0];
+    } else if constexpr (C::KIND == K_WSCAL) {
+        L.g[0][e] = (LR)q[0];
+        if (P.pde == PDE_BURGERS) {
+            L.g[1][e] = (LR)(Q(0.5) * q[0] * q[0]);
+            L.lam[e] = (LR)fabs(q[0]);
+        } else {
+            L.g[1][e] = (LR)(Q(P.c) * q[0]);
+            L.lam[e] = (LR)fabs(Q(P.c));
+        }
+    } else if constexpr (C::KIND == K_EUL) {
+        const Q gm = Q(P.gamma);
+        const Q u = q[1] / q[0];
+        const Q p = (gm - Q(1)) * (q[2] - Q(0.5) * q[1] * u);
+        for (int f = 0; f < 3; ++f) L.g[f][e] = (LR)q[f];
+        L.g[3][e] = (LR)q[1];
+        L.g[4][e] = (LR)(q[1] * u + p);
+        L.g[5][e] = (LR)(u * (q[2] + p));
+        L.lam[e] = (LR)(fabs(u) + sqrt(gm * p / q[0]));
+    } else if constexpr (C::KIND == K_REUL) {
+        double qd[4] = {(double)q[0], (double)q[1], (double)q[2], (double)q[3]};
+        double rho, u, T, Y;
+        reactive_prims(P, qd, rho, u, T, Y);
+        const double p = rho * T;
+        for (int f = 0; f < 4; ++f) L.g[f][e] = (LR)q[f];
+        L.g[4][e] = (LR)qd[1];
+        L.g[5][e] = (LR)(qd[1] * u + p);
+        L.g[6][e] = (LR)(u * (qd[2] + p));
+        L.g[7][e] = (LR)(qd[3] * u);
+        L.lam[e] = (LR)(fabs(u) + sqrt(P.gamma * T));
+    } else {  // K_RNS
+        double qd[4] = {(double)q[0], (double)q[1], (double)q[2], (double)q[3]};
+        double rho, u, T, Y;
+        reactive_prims(P, qd, rho, u, T, Y);
+        const double p = rho * T;
+        L.g[0][e] = (LR)qd[1];
+        L.g[1][e] = (LR)(qd[1] * u + p);
+        L.g[2][e] = (LR)(u * (qd[2] + p));
+        L.g[3][e] = (LR)(qd[3] * u);
+        L.g[4][e] = (LR)u;
+        L.g[5][e] = (LR)T;
+        L.g[6][e] = (LR)Y;
+    }
+}
+
+// quantity values (qreal) of a state, without writing LDS: used by the halo fill
+template <class C>
+AT_HD AT_FI void quant_values(const ProbDev& P, const typename C::qreal* q, typename C::qreal* g,
+                              typename C::qreal& lam) {
+    using Q = typename C::qreal;
+    if constexpr (C::KIND == K_ADR) {
+        g[0] = q[0];
+        lam = Q(0);
+    } else if constexpr (C::KIND == K_WSCAL) {
+        g[0] = q[0];
+        if (P.pde == PDE_BURGERS) { g[1] = Q(0.5) * q[0] * q[0]; lam = fabs(q[0]); }
+        else { g[1] = Q(P.c) * q[0]; lam = fabs(Q(P.c)); }
+    } else if constexpr (C::KIND == K_EUL) {
+        const Q gm = Q(P.gamma);
+        const Q u = q[1] / q[0];
+        const Q p = (gm - Q(1)) * (q[2] - Q(0.5) * q[1] * u);
+        g[0] = q[0]; g[1] = q[1]; g[2] = q[2];
+        g[3] = q[1]; g[4] = q[1] * u + p; g[5] = u * (q[2] + p);
+        lam = fabs(u) + sqrt(gm * p / q[0]);
+    } else if constexpr (C::KIND == K_REUL) {
+        double qd[4] = {(double)q[0], (double)q[1], (double)q[2], (double)q[3]};
+        double rho, u, T, Y;
+        reactive_prims(P, qd, rho, u, T, Y);
+        const double p = rho * T;
+        g[0] = q[0]; g[1] = q[1]; g[2] = q[2]; g[3] = q[3];
+        g[4] = qd[1]; g[5] = qd[1] * u + p; g[6] = u * (qd[2] + p); g[7] = qd[3] * u;
+        lam = fabs(u) + sqrt(P.gamma * T);
+    } else {
+        double qd[4] = {(double)q[0], (double)q[1], (double)q[2], (double)q[3]};
+        double rho, u, T, Y;
+        reactive_prims(P, qd, rho, u, T, Y);
+        const double p = rho * T;
+        g[0] = qd[1]; g[1] = qd[1] * u + p; g[2] = u * (qd[2] + p); g[3] = qd[3] * u;
+        g[4] = u; g[5] = T; g[6] = Y;
+        lam = Q(0);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// right-hand side at ext position e
+// ---------------------------------------------------------------------------
+template <class C>
+AT_HD AT_FI typename C::lreal d1(const View<typename C::lreal>& g, int64_t e) {
+    using LR = typename C::lreal;
+    LR s = LR(FD<C::H>::c1(1)) * (g[e + 1] - g[e - 1]);
+    for (int o = 2; o <= C::H; ++o) s += LR(FD<C::H>::c1(o)) * (g[e + o] - g[e - o]);
+    return s;
+}
+
+template <class C>
+AT_HD AT_FI typename C::lreal d2(const View<typename C::lreal>& g, int64_t e) {
+    using LR = typename C::lreal;
+    LR s = LR(FD<C::H>::c2(0)) * g[e];
+    for (int o = 1; o <= C::H; ++o) s += LR(FD<C::H>::c2(o)) * (g[e + o] + g[e - o]);
+    return s;
+}
+
+// WENO interface flux between e and e+1 (local Lax-Friedrichs splitting)
+template <class C>
+AT_HD AT_FI void iface_flux(const Lds<C>& L, const ProbDev& P, int64_t e) {
+    using LR = typename C::lreal;
+    const LR a0 = L.lam[e], a1 = L.lam[e + 1];
+    const LR al = a0 > a1 ? a0 : a1;
+    const LR eps = LR(P.eps);
+    const LR h = LR(0.5);
+    for (int f = 0; f < C::F; ++f) {
+        const View<LR>& Q = L.g[f];
+        const View<LR>& Cf = L.g[C::F + f];
+        LR fp[5], fm[5];
+        for (int m = 0; m < 5; ++m) {
+            fp[m] = h * (Cf[e - 2 + m] + al * Q[e - 2 + m]);
+            fm[m] = h * (Cf[e + 3 - m] - al * Q[e + 3 - m]);
+        }
+        L.flux[f][e] = weno5<LR>(eps, fp[0], fp[1], fp[2], fp[3], fp[4]) +
+                       weno5<LR>(eps, fm[0], fm[1], fm[2], fm[3], fm[4]);
+    }
+}
+
+// K at ext position e; q = the point's own state (qreal) for sources / primitives
+template <class C>
+AT_HD AT_FI void rhs_at(const Lds<C>& L, const ProbDev& P, int64_t e, const typename C::qreal* q,
+                        typename C::lreal* K) {
+    using LR = typename C::lreal;
+    if constexpr (C::KIND == K_ADR) {
+        if constexpr (C::HILO) {
+            const float hc = L.g[0][e], lc = L.glo[e];
+            float s1 = 0.f, s2 = 0.f;
+            for (int o = 1; o <= C::H; ++o) {
+                const float hp = L.g[0][e + o], hm = L.g[0][e - o];
+                const float lp = L.glo[e + o], lm = L.glo[e - o];
+                s1 += float(FD<C::H>::c1(o)) * ((hp - hm) + (lp - lm));
+                s2 += float(FD<C::H>::c2(o)) * (((hp - hc) + (lp - lc)) + ((hm - hc) + (lm - lc)));
+            }
+            float k = -float(P.c) * (s1 * float(P.inv_dx)) + float(P.alpha) * (s2 * float(P.inv_dx2));
+            if (P.pde == PDE_ADR_LOGISTIC) {
+                const float u = hc + lc;
+                k += float(P.r) * u * (1.f - u);
+            }
+            K[0] = k;
+        } else {
+            LR k = -LR(P.c) * (d1<C>(L.g[0], e) * LR(P.inv_dx)) + LR(P.alpha) * (d2<C>(L.g[0], e) * LR(P.inv_dx2));
+            if (P.pde == PDE_ADR_LOGISTIC) k += LR(P.r) * (LR)q[0] * (LR(1) - (LR)q[0]);
+            K[0] = k;
+        }
+    } else if constexpr (C::KIND == K_RNS) {
+        const LR idx = LR(P.inv_dx), idx2 = LR(P.inv_dx2);
+        double qd[4] = {(double)q[0], (double)q[1], (double)q[2], (double)q[3]};
+        double rho, u, T, Y;
+        reactive_prims(P, qd, rho, u, T, Y);
+        const LR ux = d1<C>(L.g[4], e) * idx, uxx = d2<C>(L.g[4], e) * idx2;
+        const LR Txx = d2<C>(L.g[5], e) * idx2, Yxx = d2<C>(L.g[6], e) * idx2;
+        const LR mu43 = LR(4.0 / 3.0) * LR(P.mu);
+        K[0] = -(d1<C>(L.g[0], e) * idx);
+        K[1] = -(d1<C>(L.g[1], e) * idx) + mu43 * uxx;
+        K[2] = -(d1<C>(L.g[2], e) * idx) + mu43 * (ux * ux + LR(u) * uxx) + LR(P.kappa) * Txx +
+               LR(P.q * P.rhoD) * Yxx;
+        K[3] = -(d1<C>(L.g[3], e) * idx) + LR(P.rhoD) * Yxx + LR(arrhenius(P, qd));
+    } else {  // WENO kinds
+        const LR idx = LR(P.inv_dx);
+        for (int f = 0; f < C::F; ++f) K[f] = -((L.flux[f][e] - L.flux[f][e - 1]) * idx);
+        if constexpr (C::KIND == K_REUL) {
+            double qd[4] = {(double)q[0], (double)q[1], (double)q[2], (double)q[3]};
+            K[3] += LR(arrhenius(P, qd));
+        }
+        if constexpr (C::KIND == K_WSCAL) {
+            if (P.pde == PDE_ADR_LOGISTIC) K[0] += LR(P.r) * (LR)q[0] * (LR(1) - (LR)q[0]);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// global memory helpers
+// ---------------------------------------------------------------------------
+template <class C>
+AT_HD AT_FI View<typename C::lreal> st_view(const ProbDev& P, int which) {
+    return View<typename C::lreal>{(typename C::lreal*)P.st_hi[which], (int64_t)C::F * P.n};
+}
+AT_HD AT_FI View<float> lo_view(const ProbDev& P, int which, bool f32) {
+    return View<float>{(float*)P.st_lo[which], f32 ? (int64_t)P.F * P.n : 0};
+}
+
+template <class C>
+AT_HD AT_FI unsigned char* record_ptr(const ProbDev& P, int64_t level, int64_t pe, int side) {
+    const int64_t slot = wrapi(level, P.D);
+    const int64_t idx = (slot * P.p + pe) * 2 + side;
+    AT_CHECK(idx >= 0 && idx < (int64_t)P.D * P.p * 2, "ring record", idx, (int64_t)P.D * P.p * 2);
+    return (unsigned char*)P.ring + idx * P.rec_bytes;
+}
+
+// ---------------------------------------------------------------------------
+// the tile step
+// ---------------------------------------------------------------------------
+template <class C, class RT>
+AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t, const ProbDev& P, int64_t n,
+                     unsigned char* lds_base) {
+    using LR = typename C::lreal;
+    using Q = typename C::qreal;
+    constexpr int F = C::F, H = C::H, S = C::S, PPT = C::PPT, WL = C::WL;
+
+    Layout<C> Lo;
+    Lo.init(a.npts_max, a.npe_max, a.jmax);
+    Lds<C> L;
+    L.init(lds_base, Lo, a.npe_max, a.jmax);
+
+    const int nth = rt.nthreads();
+    const int s0 = a.s_begin, s1 = a.s_end;
+    const bool first = s0 == 0;
+    const bool stage_io = (a.flags & KF_STAGE_IO) != 0;
+    const int cur = (int)(n & 1), nxt = cur ^ 1;
+    const View<LR> st = st_view<C>(P, cur);
+    const View<float> stlo = lo_view(P, cur, C::F32);
+    const bool use_lo = C::F32 && P.keep_lo;
+    const int64_t N = P.n;
+    const int J = P.J;
+    AT_CHECK(t.npts <= a.npts_max && t.npe <= a.npe_max, "tile size", t.npts, a.npts_max);
+    AT_CHECK(J <= a.jmax, "jmax", J, a.jmax);
+
+    // ---- P0: PE offsets and delays ----------------------------------------------
+    rt.each([&](int tid, TS<C>&) {
+        for (int k = tid; k <= t.npe; k += nth) {
+            const int64_t lo = ((int64_t)(t.pe0 + k) * N) / P.p;
+            L.pelo[k] = (int)(lo - t.lo);
+        }
+        for (int i = tid; i < 2 * t.npe; i += nth) {
+            const int k = i >> 1, side = i & 1;
+            const int64_t pe = t.pe0 + k;
+            int kd;
+            if (P.ov && n >= P.ov_step0 && n < P.ov_step0 + P.ov_n) {
+                const int64_t oi = ((n - P.ov_step0) * P.p + pe) * 2 + side;
+                AT_CHECK(oi >= 0 && oi < P.ov_n * P.p * 2, "override", oi, P.ov_n * P.p * 2);
+                kd = P.ov[oi];
+            } else if (P.gran == G_PE) {
+                kd = draw_delay(P, n, pe, 0);
+            } else if (P.gran == G_PE_SIDE) {
+                kd = draw_delay(P, n, pe, side);
+            } else {
+                kd = draw_delay(P, n, side == 0 ? pe : (pe + 1) % P.p, 0);
+            }
+            int ke;
+            if (P.mode == M_AT) {
+                ke = kd;
+                if ((int64_t)ke > n - (J - 1)) ke = (int)(n - (J - 1));
+                if (ke < 0) ke = 0;
+            } else if (P.mode == M_AS) {
+                ke = (int64_t)kd < n ? kd : (int)n;
+            } else {
+                ke = 0;
+            }
+            L.keff[i] = ke;
+            if ((a.flags & KF_LOG) && first && P.log_drawn) {
+                const int64_t li = (wrapi(n, P.log_cap) * P.p + pe) * 2 + side;
+                AT_CHECK(li >= 0 && li < P.log_cap * P.p * 2, "log", li, P.log_cap * P.p * 2);
+                P.log_drawn[li] = (uint8_t)kd;
+                P.log_eff[li] = (uint8_t)ke;
+            }
+        }
+    });
+    rt.sync();
+
+    // ---- P1: own points, boundary windows (level n, stage 0) -----------------------
+    rt.each([&](int tid, TS<C>& ts) {
+        for (int k = 0; k < PPT; ++k) {
+            const int i = tid + k * nth;
+            ts.e[k] = -1;
+            if (i >= t.npts) continue;
+            int lo = 0, hi = t.npe;   // pelo[lo] <= i < pelo[hi]
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (L.pelo[mid] <= i) lo = mid; else hi = mid;
+            }
+            const int e = i + 2 * H * lo + H;
+            ts.e[k] = e;
+            const int64_t x = t.lo + i;
+            ts.x[k] = x;
+            for (int f = 0; f < F; ++f) {
+                ts.uh[k][f] = st[f * N + x];
+                ts.ul[k][f] = use_lo ? stlo[f * N + x] : 0.f;
+            }
+            if (stage_io) {
+                const View<LR> kb{(LR*)P.kbuf, P.kbuf_len};
+                for (int s = 0; s < s0; ++s)
+                    for (int f = 0; f < F; ++f) ts.K[s][k][f] = kb[((int64_t)s * F + f) * N + x];
+            }
+            if (first) {   // stage-0 quantities of the own point
+                if constexpr (C::HILO) {
+                    L.g[0][e] = ts.uh[k][0];
+                    L.glo[e] = ts.ul[k][0];
+                } else {
+                    Q q[F];
+                    for (int f = 0; f < F; ++f) {
+                        if constexpr (C::F32) q[f] = (Q)ts.uh[k][f] + (Q)ts.ul[k][f];
+                        else q[f] = (Q)ts.uh[k][f];
+                    }
+                    put_quant<C>(L, P, e, q);
+                }
+            }
+        }
+        if (!first) return;
+        for (int idx = tid; idx < (t.npe + 1) * WL; idx += nth) {
+            const int b = idx / WL, w = idx % WL;
+            const int64_t x = wrapi(t.lo + L.pelo[b] - (int64_t)S * H + w, N);
+            const int64_t wp = (int64_t)b * WL + w;
+            const int64_t e = L.EXM + wp;
+            Q q[F];
+            for (int f = 0; f < F; ++f) {
+                const LR h = st[f * N + x];
+                const float l = use_lo ? stlo[f * N + x] : 0.f;
+                L.wu[f][wp] = h;
+                if constexpr (C::F32) {
+                    L.wulo[f][wp] = l;
+                    L.wq[f][wp] = l;
+                } else {
+                    L.wq[f][wp] = h;
+                }
+                if constexpr (C::F32) q[f] = (Q)h + (Q)l;
+                else q[f] = (Q)h;
+            }
+            if constexpr (C::HILO) {
+                L.g[0][e] = L.wu[0][wp];
+                L.glo[e] = L.wq[0][wp];
+            } else {
+                put_quant<C>(L, P, e, q);
+            }
+            const int h2 = w - (S - 1) * H;
+            if (h2 >= 0 && h2 < 2 * H) {
+                for (int f = 0; f < F; ++f) {
+                    L.SN[((int64_t)(b * S + 0) * 2 * H + h2) * F + f] = L.wq[f][wp];
+                    if constexpr (C::F32) L.SNhi[((int64_t)b * 2 * H + h2) * F + f] = L.wu[f][wp];
+                }
+            }
+        }
+    });
+    rt.sync();
+
+    // ---- P2: synchronous stages on the boundary windows -----------------------------
+    if (first) {
+        for (int s = 0; s + 1 < S; ++s) {
+            const int rlo = (s + 1) * H, rhi = WL - (s + 1) * H;   // R_s valid on [rlo, rhi)
+            if constexpr (C::WENO) {
+                rt.each([&](int tid, TS<C>&) {
+                    const int ni = rhi - rlo + 1;                   // interfaces rlo-1 .. rhi-1
+                    for (int idx = tid; idx < (t.npe + 1) * ni; idx += nth) {
+                        const int b = idx / ni, j = rlo - 1 + idx % ni;
+                        iface_flux<C>(L, P, L.EXM + (int64_t)b * WL + j);
+                    }
+                });
+                rt.sync();
+            }
+            rt.each([&](int tid, TS<C>&) {
+                const int nr = rhi - rlo;
+                for (int idx = tid; idx < (t.npe + 1) * nr; idx += nth) {
+                    const int b = idx / nr, w = rlo + idx % nr;
+                    const int64_t wp = (int64_t)b * WL + w;
+                    Q q[F];
+                    for (int f = 0; f < F; ++f) {
+                        if constexpr (C::F32) q[f] = (Q)L.wu[f][wp] + (Q)L.wq[f][wp];
+                        else q[f] = (Q)L.wq[f][wp];
+                    }
+                    LR K[F];
+                    rhs_at<C>(L, P, L.EXM + wp, q, K);
+                    for (int f = 0; f < F; ++f) L.wR[s][f][wp] = K[f];
+                }
+            });
+            rt.sync();
+            rt.each([&](int tid, TS<C>&) {
+                const int nr = rhi - rlo;
+                for (int idx = tid; idx < (t.npe + 1) * nr; idx += nth) {
+                    const int b = idx / nr, w = rlo + idx % nr;
+                    const int64_t wp = (int64_t)b * WL + w;
+                    const int64_t e = L.EXM + wp;
+                    Q q[F];
+                    for (int f = 0; f < F; ++f) {
+                        LR acc = LR(P.a[s + 1][0]) * L.wR[0][f][wp];
+                        for (int i = 1; i <= s; ++i) acc += LR(P.a[s + 1][i]) * L.wR[i][f][wp];
+                        if constexpr (C::F32) {
+                            const float lo = L.wulo[f][wp] + float(P.dt) * acc;
+                            L.wq[f][wp] = lo;
+                            q[f] = (Q)L.wu[f][wp] + (Q)lo;
+                        } else {
+                            const LR v = L.wu[f][wp] + LR(P.dt) * acc;
+                            L.wq[f][wp] = v;
+                            q[f] = (Q)v;
+                        }
+                    }
+                    if constexpr (C::HILO) {
+                        L.g[0][e] = L.wu[0][wp];
+                        L.glo[e] = L.wq[0][wp];
+                    } else {
+                        put_quant<C>(L, P, e, q);
+                    }
+                    const int h2 = w - (S - 1) * H;
+                    if (h2 >= 0 && h2 < 2 * H)
+                        for (int f = 0; f < F; ++f)
+                            L.SN[((int64_t)(b * S + s + 1) * 2 * H + h2) * F + f] = L.wq[f][wp];
+                }
+            });
+            rt.sync();
+        }
+    }
+
+    // ---- P3: write level-n strips, gather the delayed strips ------------------------
+    rt.each([&](int tid, TS<C>&) {
+        const int nrec = S * H * F;
+        if (first) {
+            for (int idx = tid; idx < 2 * t.npe * nrec; idx += nth) {
+                const int side_idx = idx / nrec, r = idx % nrec;
+                const int k = side_idx >> 1, side = side_idx & 1;
+                const int s = r / (H * F), h = (r / F) % H, f = r % F;
+                const int b = k + side, h2 = side * H + h;
+                unsigned char* rec = record_ptr<C>(P, n, t.pe0 + k, side);
+                const LR v = L.SN[((int64_t)(b * S + s) * 2 * H + h2) * F + f];
+                if constexpr (C::F32) {
+                    float* rf = (float*)rec;
+                    rf[H * F + (s * H + h) * F + f] = v;
+                    if (s == 0) rf[h * F + f] = L.SNhi[((int64_t)b * 2 * H + h2) * F + f];
+                } else {
+                    ((double*)rec)[(s * H + h) * F + f] = v;
+                }
+            }
+        }
+        const int per = J * nrec;
+        for (int idx = tid; idx < 2 * t.npe * per; idx += nth) {
+            const int side_idx = idx / per, r = idx % per;
+            const int l = r / nrec, rr = r % nrec;
+            const int s = rr / (H * F), h = (rr / F) % H, f = rr % F;
+            const int ke = L.keff[side_idx];
+            const int jeff = ke == 0 ? 1 : J;
+            if (l >= jeff) continue;
+            const int k = side_idx >> 1, side = side_idx & 1;
+            const int64_t m = n - ke - l;
+            const int64_t so = (int64_t)side_idx * L.SOREC + ((int64_t)(l * S + s) * H + h) * F + f;
+            const int64_t sohi = (((int64_t)side_idx * L.jmax + l) * H + h) * F + f;
+            if (m == n && first) {
+                const int b = k + side, h2 = side * H + h;
+                L.SO[so] = L.SN[((int64_t)(b * S + s) * 2 * H + h2) * F + f];
+                if constexpr (C::F32)
+                    if (s == 0) L.SOhi[sohi] = L.SNhi[((int64_t)b * 2 * H + h2) * F + f];
+            } else {
+                const unsigned char* rec = record_ptr<C>(P, m, t.pe0 + k, side);
+                if constexpr (C::F32) {
+                    const float* rf = (const float*)rec;
+                    L.SO[so] = rf[H * F + (s * H + h) * F + f];
+                    if (s == 0) L.SOhi[sohi] = rf[h * F + f];
+                } else {
+                    L.SO[so] = ((const double*)rec)[(s * H + h) * F + f];
+                }
+            }
+        }
+    });
+    rt.sync();
+
+    // ---- P4: the stages --------------------------------------------------------------
+    for (int s = s0; s <= s1; ++s) {
+        rt.each([&](int tid, TS<C>& ts) {
+            // own stage state V(s) = u^n + dt sum_{i<s} a_si K_i
+            if (s > 0 && (s > s0 || !first)) {
+                for (int k = 0; k < PPT; ++k) {
+                    const int e = ts.e[k];
+                    if (e < 0) continue;
+                    Q q[F];
+                    float vlo0 = 0.f;
+                    for (int f = 0; f < F; ++f) {
+                        LR acc = LR(P.a[s][0]) * ts.K[0][k][f];
+                        for (int i = 1; i < s; ++i) acc += LR(P.a[s][i]) * ts.K[i][k][f];
+                        if constexpr (C::F32) {
+                            const float lo = ts.ul[k][f] + float(P.dt) * acc;
+                            if (f == 0) vlo0 = lo;
+                            q[f] = (Q)ts.uh[k][f] + (Q)lo;
+                        } else {
+                            q[f] = ts.uh[k][f] + LR(P.dt) * acc;
+                        }
+                    }
+                    if constexpr (C::HILO) {
+                        L.g[0][e] = ts.uh[k][0];
+                        L.glo[e] = vlo0;
+                    } else {
+                        put_quant<C>(L, P, e, q);
+                    }
+                }
+            }
+            // halo fill: time-extrapolated synchronous stage s of the delayed levels
+            for (int idx = tid; idx < 2 * t.npe * H; idx += nth) {
+                const int side_idx = idx / H, h = idx % H;
+                const int k = side_idx >> 1, side = side_idx & 1;
+                const int ke = L.keff[side_idx];
+                const int jeff = ke == 0 ? 1 : J;
+                double w[MAXJ];
+                lagrange_weights(jeff, ke, w);
+                const int np = L.pelo[k + 1] - L.pelo[k];
+                const int64_t ebase = (int64_t)L.pelo[k] + 2 * H * k;
+                const int64_t e = side == 0 ? ebase + h : ebase + H + np + h;
+                auto sov = [&](int l, int f) -> LR {
+                    return L.SO[(int64_t)side_idx * L.SOREC + ((int64_t)(l * S + s) * H + h) * F + f];
+                };
+                auto sohi = [&](int l, int f) -> float {
+                    return L.SOhi[(((int64_t)side_idx * L.jmax + l) * H + h) * F + f];
+                };
+                if constexpr (C::HILO) {
+                    const float h0 = sohi(0, 0), l0 = sov(0, 0);
+                    float lo = l0;
+                    for (int l = 1; l < jeff; ++l)
+                        lo += float(w[l]) * ((sohi(l, 0) - h0) + (sov(l, 0) - l0));
+                    L.g[0][e] = h0;
+                    L.glo[e] = lo;
+                } else {
+                    constexpr int NQ = C::NQ;
+                    Q gl[NQ], g0[NQ], acc[NQ];
+                    for (int j = 0; j < NQ; ++j) acc[j] = g0[j] = Q(0);
+                    Q lam0 = Q(0), laml = Q(0);
+                    for (int l = 0; l < jeff; ++l) {
+                        Q q[F];
+                        for (int f = 0; f < F; ++f) {
+                            if constexpr (C::F32) q[f] = (Q)sohi(l, f) + (Q)sov(l, f);
+                            else q[f] = (Q)sov(l, f);
+                        }
+                        quant_values<C>(P, q, gl, laml);
+                        if (l == 0) {
+                            lam0 = laml;
+                            for (int j = 0; j < NQ; ++j) {
+                                g0[j] = gl[j];
+                                acc[j] = C::F32 ? gl[j] : Q(w[0]) * gl[j];
+                            }
+                        } else {
+                            for (int j = 0; j < NQ; ++j) {
+                                if constexpr (C::F32) acc[j] += Q(w[l]) * (gl[j] - g0[j]);
+                                else acc[j] += Q(w[l]) * gl[j];
+                            }
+                        }
+                    }
+                    for (int j = 0; j < NQ; ++j) L.g[j][e] = (LR)acc[j];
+                    if constexpr (C::WENO) L.lam[e] = (LR)lam0;
+                }
+            }
+        });
+        rt.sync();
+        if constexpr (C::WENO) {
+            rt.each([&](int tid, TS<C>& ts) {
+                for (int k = 0; k < PPT; ++k) {
+                    const int e = ts.e[k];
+                    if (e < 0) continue;
+                    iface_flux<C>(L, P, e);                 // right interface of the point
+                    const int i = (int)(ts.x[k] - t.lo);
+                    // left interface of the PE's first point
+                    int lo = 0, hi = t.npe;
+                    while (hi - lo > 1) {
+                        const int mid = (lo + hi) >> 1;
+                        if (L.pelo[mid] <= i) lo = mid; else hi = mid;
+                    }
+                    if (L.pelo[lo] == i) iface_flux<C>(L, P, e - 1);
+                }
+            });
+            rt.sync();
+        }
+        rt.each([&](int tid, TS<C>& ts) {
+            for (int k = 0; k < PPT; ++k) {
+                const int e = ts.e[k];
+                if (e < 0) continue;
+                Q q[F];
+                for (int f = 0; f < F; ++f) {
+                    if (s == 0) {
+                        if constexpr (C::F32) q[f] = (Q)ts.uh[k][f] + (Q)ts.ul[k][f];
+                        else q[f] = (Q)ts.uh[k][f];
+                    } else {
+                        LR acc = LR(P.a[s][0]) * ts.K[0][k][f];
+                        for (int i = 1; i < s; ++i) acc += LR(P.a[s][i]) * ts.K[i][k][f];
+                        if constexpr (C::F32) q[f] = (Q)ts.uh[k][f] + (Q)(ts.ul[k][f] + float(P.dt) * acc);
+                        else q[f] = ts.uh[k][f] + LR(P.dt) * acc;
+                    }
+                }
+                LR K[F];
+                rhs_at<C>(L, P, e, q, K);
+                for (int f = 0; f < F; ++f) ts.K[s][k][f] = K[f];
+            }
+        });
+        rt.sync();
+    }
+
+    // ---- P5: the update (or the stage output of the per-stage entry point) ----------
+    rt.each([&](int tid, TS<C>& ts) {
+        (void)tid;
+        for (int k = 0; k < PPT; ++k) {
+            if (ts.e[k] < 0) continue;
+            const int64_t x = ts.x[k];
+            if (s1 < S - 1) {
+                const View<LR> kb{(LR*)P.kbuf, P.kbuf_len};
+                for (int f = 0; f < F; ++f) kb[((int64_t)s1 * F + f) * N + x] = ts.K[s1][k][f];
+                continue;
+            }
+            const View<LR> dst = st_view<C>(P, nxt);
+            const View<float> dlo = lo_view(P, nxt, C::F32);
+            for (int f = 0; f < F; ++f) {
+                LR acc = LR(P.bw[0]) * ts.K[0][k][f];
+                for (int s = 1; s < S; ++s) acc += LR(P.bw[s]) * ts.K[s][k][f];
+                if constexpr (C::F32) {
+                    // compensated update: (hi, lo) + dt*acc, TwoSum of hi and (lo + dt*acc)
+                    const float hi = ts.uh[k][f];
+                    const float tt = ts.ul[k][f] + float(P.dt) * acc;
+                    const float sum = hi + tt;
+                    const float bb = sum - hi;
+                    const float err = (hi - (sum - bb)) + (tt - bb);
+                    dst[f * N + x] = sum;
+                    if (P.keep_lo) dlo[f * N + x] = err;
+                } else {
+                    dst[f * N + x] = ts.uh[k][f] + LR(P.dt) * acc;
+                }
+            }
+        }
+    });
+}
+
+}  // namespace atk

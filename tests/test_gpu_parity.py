@@ -1,0 +1,224 @@
+"""GPU parity of libat (through the C ABI) against the CPU oracle.
+
+Element-by-element comparison on the same seeded inputs: FP64 within 1e-12
+norm-wise relative per field, the FP32 forms within their stated bounds, and
+delay draws / effective delays bit-exact.  Launch forms (plain per-problem,
+batched, persistent, XCD-ordered, HIP-graph replay, per-stage) must agree
+bitwise with each other.
+"""
+import numpy as np
+import pytest
+
+import at_workloads as W
+import oracle
+from cases import batch_case, norm_err, single_cases, tol, with_precision
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+def solver(prs, **opts):
+    from paper_2204_01133_amd import ATSolver
+    return ATSolver(prs, **opts)
+
+
+def _oracle(pr, steps):
+    o = oracle.Oracle(pr.replace(precision="fp64"))
+    o.step(steps)
+    return o
+
+
+def test_native_library_is_loaded(torch):
+    import os
+    from paper_2204_01133_amd import binding
+    L = binding.load_library()
+    for name in binding.EXPORTED:
+        assert hasattr(L, name)
+    maps = open(f"/proc/{os.getpid()}/maps").read()
+    assert "libat.so" in maps
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32c", "fp32"])
+@pytest.mark.parametrize("name,pr,steps", single_cases(), ids=[c[0] for c in single_cases()])
+def test_gpu_matches_oracle(torch, name, pr, steps, prec):
+    print(f"case {name} {prec}", flush=True)
+    pr = with_precision(pr, prec)
+    s = solver([pr], log_steps=steps + 1)
+    s.batch_step(steps)
+    o = _oracle(pr, steps)
+    err = norm_err(pr, s.state(0), o.state())
+    assert err < tol(prec), err
+    d1, e1 = s.delays(0, 0, steps)
+    d2, e2 = o.delays(0, steps)
+    assert np.array_equal(d1, d2) and np.array_equal(e1, e2)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32c", "fp32"])
+def test_gpu_batch_matches_oracle(torch, prec):
+    prs, steps = batch_case()
+    prs = [with_precision(p, prec) for p in prs]
+    s = solver(prs)
+    s.batch_step(steps)
+    for b, pr in enumerate(prs):
+        assert norm_err(pr, s.state(b), _oracle(pr, steps).state()) < tol(prec), b
+
+
+def _run(prs, steps, method, **opts):
+    s = solver(prs, **opts)
+    getattr(s, method)(steps)
+    return [s.state(b) for b in range(len(prs))]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32c"])
+def test_launch_forms_agree_bitwise(torch, prec):
+    prs, _ = batch_case()
+    prs = [with_precision(p, prec) for p in prs]
+    steps = 13
+    ref = _run(prs, steps, "step")                                     # plain per problem
+    variants = [("batch_step", {}), ("batch_step", {"persistent": 1, "grid_per_cu": 1}),
+                ("batch_step", {"xcd_remap": 1}), ("batch_step", {"graph_steps": 4}),
+                ("batch_step", {"graph_steps": 5, "persistent": 1})]
+    for method, opts in variants:
+        got = _run(prs, steps, method, **opts)
+        for a, b in zip(got, ref):
+            assert np.array_equal(a, b), (method, opts)
+
+
+def test_graph_replay_on_torch_stream(torch):
+    prs, _ = batch_case()
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        s = solver(prs, graph_steps=3, stream=st)
+        s.batch_step(10)            # 3 replays + 1 plain step
+        s.batch_step(6)             # replays again from the device step counter
+        got = [s.state(b) for b in range(len(prs))]
+    ref = _run(prs, 16, "step")
+    for a, b in zip(got, ref):
+        assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("make", [lambda: W.adv_diff_c1(n=256, p=8, kmax=3),
+                                  lambda: W.euler_sod_c4(n=256, p=8),
+                                  lambda: W.reactive_ns_c2(n=256, p=4, precision="fp32c")])
+def test_per_stage_equals_fused(torch, make):
+    pr = make()
+    a = solver([pr], stage_api=1)
+    b = solver([pr], stage_api=1)
+    S = {"fe": 1, "rk2": 2, "ssprk3": 3, "rk4": 4}[pr.rk]
+    for _ in range(6):
+        a.step(1)
+        for s in range(1, S + 1):
+            b.rk_stage(s)
+    assert np.array_equal(a.state(0), b.state(0))
+
+
+def test_zero_override_is_bitwise_sync(torch):
+    pr = W.euler_sod_c4(n=512, p=8)
+    a = solver([pr], override_steps=20)
+    a.set_override(0, np.zeros((20, pr.p, 2), np.uint8), 0)
+    a.batch_step(20)
+    s = solver([pr.replace(mode="sync")])
+    s.batch_step(20)
+    assert np.array_equal(a.state(0), s.state(0))
+
+
+def test_sync_independent_of_pe_count(torch):
+    ref = None
+    for p in (1, 3, 8, 64, 192):
+        s = solver([W.adv_diff_c1(n=192, p=p, mode="sync")])
+        s.batch_step(25)
+        if ref is None:
+            ref = s.state(0)
+        assert np.array_equal(s.state(0), ref), p
+
+
+def test_override_schedule_and_stale_rejection(torch):
+    from paper_2204_01133_amd import ATError
+    pr = W.adv_diff_c1(n=256, p=8, kmax=3)
+    sched = np.random.default_rng(3).integers(0, 4, size=(10, 8, 2)).astype(np.uint8)
+    s = solver([pr], override_steps=10, log_steps=12)
+    s.set_override(0, sched, 2)
+    s.batch_step(12)
+    o = oracle.Oracle(pr)
+    o.set_override(2, sched)
+    o.step(12)
+    assert norm_err(pr, s.state(0), o.state()) < 1e-12
+    d, _ = s.delays(0, 2, 10)
+    assert np.array_equal(d, sched)
+    with pytest.raises(ATError) as ei:
+        s.set_override(0, np.full((2, 8, 2), 4, np.uint8), 20)
+    assert ei.value.code == -5
+
+
+def test_device_state_roundtrip(torch):
+    pr = W.euler_sod_c4(n=512, p=8, precision="fp32c")
+    s = solver([pr], set_initial=False)
+    q = torch.tensor(pr.q0, device="cuda")
+    s.set_state(0, q)
+    s.batch_step(5)
+    dev = s.state_device(0).cpu().numpy()
+    assert np.array_equal(dev, s.state(0))
+
+
+def test_api_errors(torch):
+    from paper_2204_01133_amd import ATError
+    pr = W.adv_diff_c1(n=64, p=4)
+    s = solver([pr])
+    with pytest.raises(ATError):
+        s.rk_stage(1)                      # stage buffers not reserved
+    with pytest.raises(ATError):
+        solver([pr.replace(n=10, p=20)])   # P > N
+    big = W.adv_diff_c1(n=8192, p=1)
+    with pytest.raises(ATError) as ei:
+        solver([big])                      # PE larger than a tile
+    assert ei.value.code == -2
+
+
+# --------------------------------------------------------------------------
+# full-size configurations, in the launch configuration of the benchmark
+# --------------------------------------------------------------------------
+def test_full_c1(torch):
+    pr = W.adv_diff_c1()
+    s = solver([pr], log_steps=pr.steps, graph_steps=50)
+    s.batch_step(pr.steps)
+    o = _oracle(pr, pr.steps)
+    assert norm_err(pr, s.state(0), o.state()) < 1e-12
+    assert np.array_equal(s.delays(0, 0, pr.steps)[0], o.delays(0, pr.steps)[0])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32c"])
+def test_full_c3_sampled(torch, prec):
+    prs = [p.replace(precision=prec) for p in W.batched_adr_c3()]
+    steps = prs[0].steps
+    s = solver(prs, graph_steps=50, log_steps=4)
+    s.batch_step(steps)
+    ns = np.array([p.n for p in prs])
+    pick = sorted({int(ns.argmin()), int(ns.argmax()), 0, 1, 2047, 4095,
+                   int(np.argmax([p.kmax for p in prs])), int(np.argmax([p.p for p in prs]))})
+    for b in pick:
+        assert norm_err(prs[b], s.state(b), _oracle(prs[b], steps).state()) < tol(prec), b
+    # invariants over the whole batch: finite and bounded (logistic keeps u in (0, 1.1))
+    for b in range(0, len(prs), 97):
+        u = s.state(b)
+        assert np.isfinite(u).all() and u.min() > -0.2 and u.max() < 1.3
+
+
+def test_full_c4_first_steps(torch):
+    pr = W.euler_sod_c4()
+    s = solver([pr])
+    s.batch_step(10)
+    assert norm_err(pr, s.state(0), _oracle(pr, 10).state()) < 1e-12
+
+
+def test_full_c5_first_steps(torch):
+    pr = W.detonation_c5()
+    s = solver([pr])
+    s.batch_step(5)
+    assert norm_err(pr, s.state(0), _oracle(pr, 5).state()) < tol("fp32c")
