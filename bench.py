@@ -156,11 +156,15 @@ def main():
         workers = max(1, min(16, len(os.sched_getaffinity(0))))
     except Exception:
         workers = max(1, min(16, os.cpu_count() or 1))
-    refs, owall, ocpu = oracle_sample(base, idx, total_steps, workers)
-    err32 = max(norm_err(s32.state(i), r) for i, r in zip(idx, refs))
-    err64 = max(norm_err(s64.state(i), r) for i, r in zip(idx, refs))
     sample_pts = sum(base[i].n for i in idx)
-    cpu_rate = sample_pts * S * total_steps / owall
+    if args.no_cpu_baseline:
+        err32 = err64 = None
+        cpu_rate, owall, ocpu = None, 0.0, 0.0
+    else:
+        refs, owall, ocpu = oracle_sample(base, idx, total_steps, workers)
+        err32 = max(norm_err(s32.state(i), r) for i, r in zip(idx, refs))
+        err64 = max(norm_err(s64.state(i), r) for i, r in zip(idx, refs))
+        cpu_rate = sample_pts * S * total_steps / owall
 
     traffic = None
     try:
@@ -203,7 +207,7 @@ def main():
             "bytes_per_launch": bytes32["total"],
             "avg_launch_us": t32 / K * 1e6,
         },
-        "cpu_baseline": {
+        "cpu_baseline": None if cpu_rate is None else {
             "value": cpu_rate,
             "unit": "grid-point RK-stage updates/s",
             "cores": workers,

@@ -258,15 +258,20 @@ int at_step(at_ctx* c, int n_steps) {
     for (int i = 0; i < n_steps; ++i) {
         for (size_t b = 0; b < c->plan.desc.size(); ++b) {
             const ProbInfo& pi = c->plan.info[b];
-            const Group& g = c->plan.groups[pi.group];
-            KArgs a = base_args(c, g);
-            a.tiles = (const Tile*)(c->ws + c->plan.off_tiles_pm) + pi.t0;
-            a.ntiles = pi.ntiles;
-            a.step_off = c->step;
-            a.s_begin = 0;
-            a.s_end = pi.S - 1;
-            rc = launch_key(c, pi.key, a, pi.ntiles);
-            if (rc) return rc;
+            for (int cls = 0; cls < 2; ++cls) {
+                if (pi.gid[cls] < 0) continue;
+                const Group& g = c->plan.groups[pi.gid[cls]];
+                KArgs a = base_args(c, g);
+                const int off = cls ? pi.ntiles_small : 0;
+                const int cnt = cls ? pi.ntiles - pi.ntiles_small : pi.ntiles_small;
+                a.tiles = (const Tile*)(c->ws + c->plan.off_tiles_pm) + pi.t0 + off;
+                a.ntiles = cnt;
+                a.step_off = c->step;
+                a.s_begin = 0;
+                a.s_end = pi.S - 1;
+                rc = launch_key(c, g.key, a, cnt);
+                if (rc) return rc;
+            }
         }
         c->step += 1;
     }

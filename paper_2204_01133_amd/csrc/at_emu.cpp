@@ -92,10 +92,10 @@ static int run_all(EmuCtx& c, int s_begin, int s_end, int flags) {
     for (const Group& g : c.plan.groups) {
         const int se = s_end < 0 ? g.key.S - 1 : s_end;
         bool done = false;
-#define AT_EMU_CASE(K, H_, S_, F32_)                                                      \
+#define AT_EMU_CASE(K, H_, S_, F32_, PPT_)                                                \
         if (!done && g.key.kind == (K) && g.key.H == (H_) && g.key.S == (S_) &&          \
-            g.key.f32 == ((F32_) != 0)) {                                               \
-            run_group<AT_CFG(K, H_, S_, F32_)>(c, g, s_begin, se, flags);               \
+            g.key.f32 == ((F32_) != 0) && g.key.ppt == (PPT_)) {                        \
+            run_group<AT_CFG(K, H_, S_, F32_, PPT_)>(c, g, s_begin, se, flags);         \
             done = true;                                                                 \
         }
         AT_VARIANTS(AT_EMU_CASE)

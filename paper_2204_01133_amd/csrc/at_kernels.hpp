@@ -62,9 +62,10 @@ bool launch_reul(const VariantKey& k, const KArgs& a, int grid, hipStream_t s, h
 
 }  // namespace atk
 
-#define AT_LAUNCH_CASE(K, H_, S_, F32_)                                               \
-    if (k.kind == (K) && k.H == (H_) && k.S == (S_) && k.f32 == ((F32_) != 0)) {      \
-        *e = launch_variant<AT_CFG(K, H_, S_, F32_)>(a, grid, s);                     \
+#define AT_LAUNCH_CASE(K, H_, S_, F32_, PPT_)                                         \
+    if (k.kind == (K) && k.H == (H_) && k.S == (S_) && k.f32 == ((F32_) != 0) &&      \
+        k.ppt == (PPT_)) {                                                            \
+        *e = launch_variant<AT_CFG(K, H_, S_, F32_, PPT_)>(a, grid, s);               \
         return true;                                                                  \
     }
 

@@ -21,9 +21,10 @@ std::string fmt(const char* f, long long a = 0, long long b = 0, long long c = 0
 
 bool variant_sizes(const VariantKey& v, int npts_max, int npe_max, int jmax, int64_t* lds_bytes,
                    int64_t* rec_bytes) {
-#define AT_SIZE_CASE(K, H_, S_, F32_)                                              \
-    if (v.kind == (K) && v.H == (H_) && v.S == (S_) && v.f32 == ((F32_) != 0)) {   \
-        using C = AT_CFG(K, H_, S_, F32_);                                         \
+#define AT_SIZE_CASE(K, H_, S_, F32_, PPT_)                                        \
+    if (v.kind == (K) && v.H == (H_) && v.S == (S_) && v.f32 == ((F32_) != 0) &&   \
+        v.ppt == (PPT_)) {                                                         \
+        using C = AT_CFG(K, H_, S_, F32_, PPT_);                                   \
         Layout<C> lo;                                                              \
         lo.init(npts_max, npe_max, jmax);                                          \
         *lds_bytes = lo.total;                                                     \
@@ -155,7 +156,8 @@ int make_plan(const at_problem_desc* probs, int n_probs, const at_run_opts* opts
         int S;
         double a[MAXS][MAXS], bw[MAXS];
         rk_tableau(d.rk, &S, a, bw);
-        pi.key = VariantKey{kind_of(d.pde, d.scheme), halo_of(d.scheme), S, d.precision != AT_FP64};
+        const int kind = kind_of(d.pde, d.scheme);
+        pi.key = VariantKey{kind, halo_of(d.scheme), S, d.precision != AT_FP64, ppt_small(kind)};
         pi.F = fields_of(d.pde);
         pi.H = pi.key.H;
         pi.S = S;
@@ -168,34 +170,38 @@ int make_plan(const at_problem_desc* probs, int n_probs, const at_run_opts* opts
         plan.max_jmax = std::max(plan.max_jmax, pi.J);
     }
 
-    // ---- tiles: whole PEs packed up to the tile target and the LDS budget ----
-    const int64_t lds_budget = 64 * 1024;
+    // ---- tiles: whole PEs packed up to the tile target and the LDS budget; a PE
+    //      larger than a small tile gets a tile of the large points-per-thread class ----
+    const int64_t lds_budget = 48 * 1024;
     const int64_t lds_hard = 160 * 1024;
-    std::vector<std::vector<Tile>> per_prob(n_probs);
+    std::vector<std::vector<Tile>> small(n_probs), large(n_probs);
     for (int b = 0; b < n_probs; ++b) {
         const at_problem_desc& d = plan.desc[b];
         ProbInfo& pi = plan.info[b];
-        const int ppt = ppt_of(pi.key.kind);
-        const int tmax = BLOCK * ppt;
-        int target = plan.opts.tile_points > 0 ? plan.opts.tile_points
-                                               : (ppt == 8 ? 1024 : 512);
-        target = std::min(target, tmax);
+        VariantKey ks = pi.key, kl = pi.key;
+        kl.ppt = ppt_large(pi.key.kind);
+        const int tsmall = BLOCK * ks.ppt, tlarge = BLOCK * kl.ppt;
+        const int target = plan.opts.tile_points > 0 ? std::min(plan.opts.tile_points, tsmall) : tsmall;
         Tile cur{b, 0, 0, 0, 0};
         auto pe_lo = [&](int64_t k) { return (k * d.n) / d.p; };
         for (int64_t k = 0; k < d.p; ++k) {
             const int64_t np = pe_lo(k + 1) - pe_lo(k);
-            if (np > tmax) {
-                err = fmt("problem %lld: PE of %lld points exceeds the tile limit %lld", b, np, tmax);
+            if (np > tlarge) {
+                err = fmt("problem %lld: PE of %lld points exceeds the tile limit %lld", b, np, tlarge);
                 return AT_EUNSUPPORTED;
+            }
+            if (np > target) {
+                large[b].push_back(Tile{b, (int32_t)k, 1, (int32_t)np, pe_lo(k)});
+                continue;
             }
             bool fits = cur.npe > 0 && cur.npts + np <= target;
             if (fits) {
                 int64_t lds, rec;
-                variant_sizes(pi.key, (int)(cur.npts + np), cur.npe + 1, pi.J, &lds, &rec);
+                variant_sizes(ks, (int)(cur.npts + np), cur.npe + 1, pi.J, &lds, &rec);
                 fits = lds <= lds_budget;
             }
             if (!fits && cur.npe > 0) {
-                per_prob[b].push_back(cur);
+                small[b].push_back(cur);
                 cur = Tile{b, 0, 0, 0, 0};
             }
             if (cur.npe == 0) {
@@ -205,49 +211,58 @@ int make_plan(const at_problem_desc* probs, int n_probs, const at_run_opts* opts
             cur.npe += 1;
             cur.npts += (int32_t)np;
         }
-        if (cur.npe > 0) per_prob[b].push_back(cur);
-        for (const Tile& t : per_prob[b]) {
-            int64_t lds, rec;
-            variant_sizes(pi.key, t.npts, t.npe, pi.J, &lds, &rec);
-            if (lds > lds_hard) {
-                err = fmt("problem %lld: tile needs %lld bytes of LDS", b, lds);
-                return AT_EUNSUPPORTED;
+        if (cur.npe > 0) small[b].push_back(cur);
+        for (int cls = 0; cls < 2; ++cls)
+            for (const Tile& t : (cls ? large[b] : small[b])) {
+                int64_t lds, rec;
+                variant_sizes(cls ? kl : ks, t.npts, t.npe, pi.J, &lds, &rec);
+                if (lds > lds_hard) {
+                    err = fmt("problem %lld: tile needs %lld bytes of LDS", b, lds);
+                    return AT_EUNSUPPORTED;
+                }
             }
-        }
     }
-    for (int b = 0; b < n_probs; ++b) {
-        plan.info[b].t0 = (int)plan.tiles_pm.size();
-        plan.info[b].ntiles = (int)per_prob[b].size();
-        plan.tiles_pm.insert(plan.tiles_pm.end(), per_prob[b].begin(), per_prob[b].end());
-    }
-
-    // ---- groups (kernel variants), batched order sorted by cost ----
     for (int b = 0; b < n_probs; ++b) {
         ProbInfo& pi = plan.info[b];
-        int gid = -1;
-        for (size_t g = 0; g < plan.groups.size(); ++g)
-            if (plan.groups[g].key == pi.key) gid = (int)g;
-        if (gid < 0) {
-            Group g;
-            g.key = pi.key;
-            g.ppt = ppt_of(pi.key.kind);
-            g.t0 = g.ntiles = 0;
-            g.npts_max = g.npe_max = 0;
-            g.jmax = 1;
-            g.lds_bytes = 0;
-            plan.groups.push_back(g);
-            gid = (int)plan.groups.size() - 1;
-        }
-        pi.group = gid;
-        plan.groups[gid].probs.push_back(b);
+        pi.t0 = (int)plan.tiles_pm.size();
+        pi.ntiles_small = (int)small[b].size();
+        pi.ntiles = pi.ntiles_small + (int)large[b].size();
+        plan.tiles_pm.insert(plan.tiles_pm.end(), small[b].begin(), small[b].end());
+        plan.tiles_pm.insert(plan.tiles_pm.end(), large[b].begin(), large[b].end());
     }
-    for (Group& g : plan.groups) {
-        std::vector<Tile> ts;
-        for (int b : g.probs) {
-            const ProbInfo& pi = plan.info[b];
+
+    // ---- groups (kernel variants incl. tile class), batched order sorted by cost ----
+    auto group_of = [&](const VariantKey& k) {
+        for (size_t g = 0; g < plan.groups.size(); ++g)
+            if (plan.groups[g].key == k) return (int)g;
+        Group g;
+        g.key = k;
+        g.t0 = g.ntiles = 0;
+        g.npts_max = g.npe_max = 0;
+        g.jmax = 1;
+        g.lds_bytes = 0;
+        plan.groups.push_back(g);
+        return (int)plan.groups.size() - 1;
+    };
+    std::vector<std::vector<Tile>> gtiles;
+    for (int b = 0; b < n_probs; ++b) {
+        ProbInfo& pi = plan.info[b];
+        VariantKey kl = pi.key;
+        kl.ppt = ppt_large(pi.key.kind);
+        pi.gid[0] = pi.ntiles_small ? group_of(pi.key) : -1;
+        pi.gid[1] = pi.ntiles > pi.ntiles_small ? group_of(kl) : -1;
+        gtiles.resize(plan.groups.size());
+        for (int i = 0; i < pi.ntiles; ++i) {
+            const int cls = i < pi.ntiles_small ? 0 : 1;
+            Group& g = plan.groups[pi.gid[cls]];
             g.jmax = std::max(g.jmax, pi.J);
-            for (int i = 0; i < pi.ntiles; ++i) ts.push_back(plan.tiles_pm[pi.t0 + i]);
+            if (std::find(g.probs.begin(), g.probs.end(), b) == g.probs.end()) g.probs.push_back(b);
+            gtiles[pi.gid[cls]].push_back(plan.tiles_pm[pi.t0 + i]);
         }
+    }
+    for (size_t gi = 0; gi < plan.groups.size(); ++gi) {
+        Group& g = plan.groups[gi];
+        std::vector<Tile>& ts = gtiles[gi];
         const int wl = 2 * g.key.S * g.key.H;
         auto cost = [&](const Tile& t) { return (int64_t)t.npts + (int64_t)(t.npe + 1) * wl; };
         std::stable_sort(ts.begin(), ts.end(), [&](const Tile& x, const Tile& y) { return cost(x) > cost(y); });
@@ -260,6 +275,10 @@ int make_plan(const at_problem_desc* probs, int n_probs, const at_run_opts* opts
         plan.tiles_bt.insert(plan.tiles_bt.end(), ts.begin(), ts.end());
         int64_t rec;
         variant_sizes(g.key, g.npts_max, g.npe_max, g.jmax, &g.lds_bytes, &rec);
+        if (g.lds_bytes > lds_hard) {
+            err = fmt("kernel group needs %lld bytes of LDS", g.lds_bytes);
+            return AT_EUNSUPPORTED;
+        }
     }
 
     // ---- workspace layout ----

@@ -16,14 +16,12 @@ namespace atk {
 
 constexpr int BLOCK = 256;          // threads per workgroup of the tile kernels
 
-// Points per thread of each kernel kind (registers hold u^n and the S stage RHS).
-inline int ppt_of(int kind) { return (kind == K_ADR || kind == K_WSCAL) ? 8 : 4; }
-
 struct VariantKey {
     int kind, H, S;
     bool f32;
+    int ppt;      // points per thread: tiles of at most BLOCK * ppt points
     bool operator==(const VariantKey& o) const {
-        return kind == o.kind && H == o.H && S == o.S && f32 == o.f32;
+        return kind == o.kind && H == o.H && S == o.S && f32 == o.f32 && ppt == o.ppt;
     }
 };
 
@@ -32,9 +30,11 @@ bool variant_sizes(const VariantKey& v, int npts_max, int npe_max, int jmax, int
                    int64_t* rec_bytes);
 
 struct ProbInfo {
-    VariantKey key;
-    int F, J, D, S, H, group;
+    VariantKey key;           // small-tile variant (ppt_small)
+    int F, J, D, S, H;
     int ntiles, t0;            // problem-major tile range [t0, t0 + ntiles)
+    int ntiles_small;          // the first ntiles_small tiles are of the small class
+    int gid[2];                // group of the small / large tile class (-1: none)
     int64_t st_elems;          // F * N
     size_t off_hi[2], off_lo[2], off_ring, off_kbuf, off_ov, off_log_d, off_log_e;
     int64_t rec_bytes, ring_bytes, kbuf_len;
@@ -43,7 +43,6 @@ struct ProbInfo {
 
 struct Group {
     VariantKey key;
-    int ppt;
     int t0, ntiles;            // range in the batched (group-major) tile array
     int npts_max, npe_max, jmax;
     int64_t lds_bytes;

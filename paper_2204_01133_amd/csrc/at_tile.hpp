@@ -134,34 +134,40 @@ struct Cfg {
 AT_HD AT_FI int64_t align16(int64_t b) { return (b + 15) & ~int64_t(15); }
 
 // LDS layout of a launch (same function on host and device).
+//   main region (per PE of the tile: H halo slots, own points, H halo slots)
+//   window region (one window of 2*S*H positions per PE boundary), with the
+//   quantities double-buffered by stage parity so that stage s+1 of a window
+//   is written while stage s is still being read.
 template <class C>
 struct Layout {
-    int64_t EXM, EXW, EX, NW, SOREC;
-    int64_t o_g, o_glo, o_lam, o_flux, o_wu, o_wulo, o_wq, o_wR, o_SN, o_SNhi, o_SO, o_SOhi,
-        o_pelo, o_keff, total;
+    int64_t EXM, EXW, NW, SOREC;
+    int64_t o_g, o_glo, o_lam, o_flux, o_gw, o_gwlo, o_lamw, o_fluxw, o_wu, o_wulo, o_wq, o_wR,
+        o_SO, o_SOhi, o_pelo, o_keff, total;
     AT_HD void init(int npts_max, int npe_max, int jmax) {
         using L = typename C::lreal;
         const int64_t sl = (int64_t)sizeof(L);
         EXM = npts_max + 2 * C::H * (int64_t)npe_max;
         NW = npe_max + 1;
         EXW = NW * C::WL;
-        EX = EXM + EXW;
         SOREC = (int64_t)jmax * C::S * C::H * C::F;  // per PE side
+        const int64_t SR = C::S > 1 ? C::S - 1 : 1;
         int64_t o = 0;
-        o_g = o;    o += align16(C::NQ * EX * sl);
-        o_glo = o;  o += C::HILO ? align16(EX * 4) : 0;
-        o_lam = o;  o += C::WENO ? align16(EX * sl) : 0;
-        o_flux = o; o += C::WENO ? align16(C::F * EX * sl) : 0;
-        o_wu = o;   o += align16(C::F * EXW * sl);
-        o_wulo = o; o += C::F32 ? align16(C::F * EXW * 4) : 0;
-        o_wq = o;   o += align16(C::F * EXW * sl);
-        o_wR = o;   o += align16((C::S > 1 ? C::S - 1 : 1) * C::F * EXW * sl);
-        o_SN = o;   o += align16(NW * C::S * 2 * C::H * C::F * sl);
-        o_SNhi = o; o += C::F32 ? align16(NW * 2 * C::H * C::F * 4) : 0;
-        o_SO = o;   o += align16(2 * (int64_t)npe_max * SOREC * sl);
-        o_SOhi = o; o += C::F32 ? align16(2 * (int64_t)npe_max * jmax * C::H * C::F * 4) : 0;
-        o_pelo = o; o += align16((npe_max + 1) * 4);
-        o_keff = o; o += align16(2 * (int64_t)npe_max * 4);
+        o_g = o;     o += align16(C::NQ * EXM * sl);
+        o_glo = o;   o += C::HILO ? align16(EXM * 4) : 0;
+        o_lam = o;   o += C::WENO ? align16(EXM * sl) : 0;
+        o_flux = o;  o += C::WENO ? align16(C::F * EXM * sl) : 0;
+        o_gw = o;    o += align16(2 * C::NQ * EXW * sl);
+        o_gwlo = o;  o += C::HILO ? align16(2 * EXW * 4) : 0;
+        o_lamw = o;  o += C::WENO ? align16(2 * EXW * sl) : 0;
+        o_fluxw = o; o += C::WENO ? align16(C::F * EXW * sl) : 0;
+        o_wu = o;    o += align16(C::F * EXW * sl);
+        o_wulo = o;  o += C::F32 ? align16(C::F * EXW * 4) : 0;
+        o_wq = o;    o += align16(2 * C::F * EXW * sl);
+        o_wR = o;    o += align16(SR * C::F * EXW * sl);
+        o_SO = o;    o += align16(2 * (int64_t)npe_max * SOREC * sl);
+        o_SOhi = o;  o += C::F32 ? align16(2 * (int64_t)npe_max * jmax * C::H * C::F * 4) : 0;
+        o_pelo = o;  o += align16((npe_max + 1) * 4);
+        o_keff = o;  o += align16(2 * (int64_t)npe_max * 4);
         total = o;
     }
 };
@@ -194,16 +200,20 @@ AT_HD AT_FI int draw_delay(const ProbDev& P, int64_t step, int64_t idx, int side
     return k;
 }
 
-// Lagrange weights from levels -k..-k-J+1 to 0: w_l = prod_{m!=l} (k+m)/(m-l), exact integers.
-AT_HD AT_FI void lagrange_weights(int J, int k, double* w) {
-    for (int l = 0; l < J; ++l) {
+// Lagrange weights from levels -k..-k-J+1 to 0: w_l = prod_{m!=l} (k+m)/(m-l), exact
+// integers; fixed-size loops (JM >= J) so that w stays in registers.
+constexpr int JM = 6;
+AT_HD AT_FI void lagrange_weights(int J, int k, double (&w)[JM]) {
+#pragma unroll
+    for (int l = 0; l < JM; ++l) {
         int64_t num = 1, den = 1;
-        for (int m = 0; m < J; ++m) {
-            if (m == l) continue;
+#pragma unroll
+        for (int m = 0; m < JM; ++m) {
+            if (m == l || m >= J) continue;
             num *= (int64_t)(k + m);
             den *= (int64_t)(m - l);
         }
-        w[l] = (double)(num / den);
+        w[l] = l < J ? (double)(num / den) : 0.0;
     }
 }
 
@@ -273,54 +283,79 @@ AT_HD AT_FI R weno5(R eps, R v0, R v1, R v2, R v3, R v4) {
 }
 
 // ---------------------------------------------------------------------------
-// per-thread state (registers on the GPU)
+// per-thread state (registers on the GPU: every index below is a compile-time
+// constant after unrolling)
 // ---------------------------------------------------------------------------
 template <class C>
 struct TS {
     int e[C::PPT];                                // ext index of the own point (-1: none)
-    int64_t x[C::PPT];                            // global point index
     typename C::lreal uh[C::PPT][C::F];           // u^n (FP64 value / FP32 hi)
     float ul[C::PPT][C::F];                       // FP32 lo
     typename C::lreal K[C::S][C::PPT][C::F];      // stage right-hand sides
+};
+
+// views of one set of differentiated quantities (main region or one window parity)
+template <class C>
+struct QV {
+    using L = typename C::lreal;
+    View<L> g[C::NQ];
+    View<float> glo;      // HILO: lo part of g[0]
+    View<L> lam;          // WENO: wave speed
+    View<L> flux[C::F];   // WENO: interface flux between e and e+1 at e
 };
 
 // LDS views of one launch
 template <class C>
 struct Lds {
     using L = typename C::lreal;
-    View<L> g[C::NQ];
-    View<float> glo;
-    View<L> lam;
-    View<L> flux[C::F];
-    View<L> wu[C::F], wq[C::F];
+    static constexpr int SR = C::S > 1 ? C::S - 1 : 1;
+    QV<C> main, win[2];
+    View<L> wu[C::F], wq[2][C::F];
     View<float> wulo[C::F];
-    View<L> wR[C::S > 1 ? C::S - 1 : 1][C::F];
-    View<L> SN, SO;
-    View<float> SNhi, SOhi;
+    View<L> wR[SR][C::F];
+    View<L> SO;
+    View<float> SOhi;
     View<int> pelo, keff;
-    int64_t EXM, EX, EXW, SOREC;
-    int jmax;
+    int EXM, EXW, SOREC, jmax;
     AT_HD void init(unsigned char* base, const Layout<C>& Lo, int npe_max, int jm) {
-        EXM = Lo.EXM; EX = Lo.EX; EXW = Lo.EXW; SOREC = Lo.SOREC; jmax = jm;
-        for (int q = 0; q < C::NQ; ++q) g[q] = View<L>{(L*)(base + Lo.o_g) + q * EX, EX};
-        glo = View<float>{(float*)(base + Lo.o_glo), C::HILO ? EX : 0};
-        lam = View<L>{(L*)(base + Lo.o_lam), C::WENO ? EX : 0};
-        for (int f = 0; f < C::F; ++f) {
-            flux[f] = View<L>{(L*)(base + Lo.o_flux) + f * EX, C::WENO ? EX : 0};
-            wu[f] = View<L>{(L*)(base + Lo.o_wu) + f * EXW, EXW};
-            wq[f] = View<L>{(L*)(base + Lo.o_wq) + f * EXW, EXW};
-            wulo[f] = View<float>{(float*)(base + Lo.o_wulo) + f * EXW, C::F32 ? EXW : 0};
-            for (int s = 0; s < (C::S > 1 ? C::S - 1 : 1); ++s)
-                wR[s][f] = View<L>{(L*)(base + Lo.o_wR) + (s * C::F + f) * EXW, EXW};
+        EXM = (int)Lo.EXM; EXW = (int)Lo.EXW; SOREC = (int)Lo.SOREC; jmax = jm;
+        const int64_t nm = Lo.EXM, nw = Lo.EXW;
+        for (int q = 0; q < C::NQ; ++q) {
+            main.g[q] = View<L>{(L*)(base + Lo.o_g) + q * nm, nm};
+            for (int par = 0; par < 2; ++par)
+                win[par].g[q] = View<L>{(L*)(base + Lo.o_gw) + (par * C::NQ + q) * nw, nw};
         }
-        SN = View<L>{(L*)(base + Lo.o_SN), Lo.NW * C::S * 2 * C::H * C::F};
-        SNhi = View<float>{(float*)(base + Lo.o_SNhi), C::F32 ? Lo.NW * 2 * C::H * C::F : 0};
-        SO = View<L>{(L*)(base + Lo.o_SO), 2 * (int64_t)npe_max * SOREC};
+        main.glo = View<float>{(float*)(base + Lo.o_glo), C::HILO ? nm : 0};
+        main.lam = View<L>{(L*)(base + Lo.o_lam), C::WENO ? nm : 0};
+        for (int par = 0; par < 2; ++par) {
+            win[par].glo = View<float>{(float*)(base + Lo.o_gwlo) + par * nw, C::HILO ? nw : 0};
+            win[par].lam = View<L>{(L*)(base + Lo.o_lamw) + par * nw, C::WENO ? nw : 0};
+        }
+        for (int f = 0; f < C::F; ++f) {
+            main.flux[f] = View<L>{(L*)(base + Lo.o_flux) + f * nm, C::WENO ? nm : 0};
+            win[0].flux[f] = win[1].flux[f] = View<L>{(L*)(base + Lo.o_fluxw) + f * nw, C::WENO ? nw : 0};
+            wu[f] = View<L>{(L*)(base + Lo.o_wu) + f * nw, nw};
+            wulo[f] = View<float>{(float*)(base + Lo.o_wulo) + f * nw, C::F32 ? nw : 0};
+            for (int par = 0; par < 2; ++par)
+                wq[par][f] = View<L>{(L*)(base + Lo.o_wq) + (par * C::F + f) * nw, nw};
+            for (int r = 0; r < SR; ++r)
+                wR[r][f] = View<L>{(L*)(base + Lo.o_wR) + (r * C::F + f) * nw, nw};
+        }
+        SO = View<L>{(L*)(base + Lo.o_SO), 2 * (int64_t)npe_max * Lo.SOREC};
         SOhi = View<float>{(float*)(base + Lo.o_SOhi), C::F32 ? 2 * (int64_t)npe_max * jm * C::H * C::F : 0};
         pelo = View<int>{(int*)(base + Lo.o_pelo), npe_max + 1};
         keff = View<int>{(int*)(base + Lo.o_keff), 2 * (int64_t)npe_max};
     }
 };
+
+// compile-time loop: f(std::integral_constant<int, I>) for I in [B, E)
+template <int B, int E, class Fn>
+AT_HD AT_FI void static_for(Fn&& f) {
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        static_for<B + 1, E>(f);
+    }
+}
 
 AT_HD AT_FI int64_t wrapi(int64_t x, int64_t n) {
     int64_t r = x % n;
@@ -332,7 +367,7 @@ AT_HD AT_FI int64_t wrapi(int64_t x, int64_t n) {
 // ---------------------------------------------------------------------------
 // q: full state at the point (qreal).  For HILO the caller writes hi/lo itself.
 template <class C>
-AT_HD AT_FI void put_quant(const Lds<C>& L, const ProbDev& P, int64_t e, const typename C::qreal* q) {
+AT_HD AT_FI void put_quant(const QV<C>& L, const ProbDev& P, int64_t e, const typename C::qreal* q) {
     using Q = typename C::qreal;
     using LR = typename C::lreal;
     if constexpr (C::KIND == K_ADR) {
@@ -440,7 +475,7 @@ AT_HD AT_FI typename C::lreal d2(const View<typename C::lreal>& g, int64_t e) {
 
 // WENO interface flux between e and e+1 (local Lax-Friedrichs splitting)
 template <class C>
-AT_HD AT_FI void iface_flux(const Lds<C>& L, const ProbDev& P, int64_t e) {
+AT_HD AT_FI void iface_flux(const QV<C>& L, const ProbDev& P, int64_t e) {
     using LR = typename C::lreal;
     const LR a0 = L.lam[e], a1 = L.lam[e + 1];
     const LR al = a0 > a1 ? a0 : a1;
@@ -461,7 +496,7 @@ AT_HD AT_FI void iface_flux(const Lds<C>& L, const ProbDev& P, int64_t e) {
 
 // K at ext position e; q = the point's own state (qreal) for sources / primitives
 template <class C>
-AT_HD AT_FI void rhs_at(const Lds<C>& L, const ProbDev& P, int64_t e, const typename C::qreal* q,
+AT_HD AT_FI void rhs_at(const QV<C>& L, const ProbDev& P, int64_t e, const typename C::qreal* q,
                         typename C::lreal* K) {
     using LR = typename C::lreal;
     if constexpr (C::KIND == K_ADR) {
@@ -532,13 +567,25 @@ AT_HD AT_FI unsigned char* record_ptr(const ProbDev& P, int64_t level, int64_t p
 
 // ---------------------------------------------------------------------------
 // the tile step
+//
+//   P0  PE offsets, delays
+//   P1  own points (registers, stage-s0 quantities), boundary windows of level n
+//       (stage-0 quantities, ring records of stage 0), delayed strips -> LDS
+//   per stage s:  A  own quantities of V(s), halo fill (extrapolated strips, or
+//                    the window's synchronous stage s when the delay is 0)
+//                 B  [WENO: interface fluxes]  K_s at own points; R_s on the
+//                    windows and their synchronous stage s+1 (+ ring record)
+//   P5  u^{n+1} (or K_s to the workspace in per-stage mode)
 // ---------------------------------------------------------------------------
+template <class C>
+AT_HD AT_FI int64_t ring_lo_off(int s, int h, int f) { return (int64_t)C::H * C::F + ((int64_t)s * C::H + h) * C::F + f; }
+
 template <class C, class RT>
 AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t, const ProbDev& P, int64_t n,
                      unsigned char* lds_base) {
     using LR = typename C::lreal;
     using Q = typename C::qreal;
-    constexpr int F = C::F, H = C::H, S = C::S, PPT = C::PPT, WL = C::WL;
+    constexpr int F = C::F, H = C::H, S = C::S, PPT = C::PPT, WL = C::WL, NQ = C::NQ;
 
     Layout<C> Lo;
     Lo.init(a.npts_max, a.npe_max, a.jmax);
@@ -555,8 +602,32 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t, const ProbDev& P, in
     const bool use_lo = C::F32 && P.keep_lo;
     const int64_t N = P.n;
     const int J = P.J;
+    const LR dt = LR(P.dt);
     AT_CHECK(t.npts <= a.npts_max && t.npe <= a.npe_max, "tile size", t.npts, a.npts_max);
-    AT_CHECK(J <= a.jmax, "jmax", J, a.jmax);
+    AT_CHECK(J <= a.jmax && J <= JM, "jmax", J, a.jmax);
+    AT_CHECK(t.npts <= nth * PPT, "points per thread", t.npts, nth * PPT);
+
+    // ring record of PE (t.pe0 + k), side, level n: stage s at halo point h
+    auto rec_store = [&](int k, int side, int s, int h, int f, LR v, float hi) {
+        unsigned char* rec = record_ptr<C>(P, n, t.pe0 + k, side);
+        if constexpr (C::F32) {
+            float* rf = (float*)rec;
+            rf[ring_lo_off<C>(s, h, f)] = v;
+            if (s == 0) rf[h * F + f] = hi;
+        } else {
+            ((double*)rec)[((int64_t)s * H + h) * F + f] = v;
+        }
+    };
+    // write the window's synchronous-stage strip value at window position w of boundary b
+    auto strip_out = [&](int b, int w, int s, int f, LR v, float hi) {
+        const int h2 = w - (S - 1) * H;
+        if (h2 < 0 || h2 >= 2 * H) return;
+        if (h2 < H) {                       // left halo of PE b
+            if (b < t.npe) rec_store(b, 0, s, h2, f, v, hi);
+        } else {                            // right halo of PE b-1
+            if (b >= 1) rec_store(b - 1, 1, s, h2 - H, f, v, hi);
+        }
+    };
 
     // ---- P0: PE offsets and delays ----------------------------------------------
     rt.each([&](int tid, TS<C>&) {
@@ -600,8 +671,44 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t, const ProbDev& P, in
     });
     rt.sync();
 
-    // ---- P1: own points, boundary windows (level n, stage 0) -----------------------
+    // own stage state V(s) = u^n + dt sum_{i<s} a_si K_i of slot k, field f
+    auto own_state = [&](const TS<C>& ts, int k, int f, auto sc, float& vlo) -> Q {
+        constexpr int s = decltype(sc)::value;
+        if constexpr (s == 0) {
+            vlo = ts.ul[k][f];
+            if constexpr (C::F32) return (Q)ts.uh[k][f] + (Q)ts.ul[k][f];
+            else return (Q)ts.uh[k][f];
+        } else {
+            LR acc = LR(P.a[s][0]) * ts.K[0][k][f];
+#pragma unroll
+            for (int i = 1; i < s; ++i) acc += LR(P.a[s][i]) * ts.K[i][k][f];
+            if constexpr (C::F32) {
+                const float lo = ts.ul[k][f] + float(dt) * acc;
+                vlo = lo;
+                return (Q)ts.uh[k][f] + (Q)lo;
+            } else {
+                vlo = 0.f;
+                return (Q)(ts.uh[k][f] + dt * acc);
+            }
+        }
+    };
+    auto own_quant = [&](const TS<C>& ts, int k, auto sc) {
+        const int e = ts.e[k];
+        Q q[F];
+        float vlo[F];
+#pragma unroll
+        for (int f = 0; f < F; ++f) q[f] = own_state(ts, k, f, sc, vlo[f]);
+        if constexpr (C::HILO) {
+            L.main.g[0][e] = ts.uh[k][0];
+            L.main.glo[e] = vlo[0];
+        } else {
+            put_quant<C>(L.main, P, e, q);
+        }
+    };
+
+    // ---- P1: own points, boundary windows, delayed strips ---------------------------
     rt.each([&](int tid, TS<C>& ts) {
+#pragma unroll
         for (int k = 0; k < PPT; ++k) {
             const int i = tid + k * nth;
             ts.e[k] = -1;
@@ -611,340 +718,305 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t, const ProbDev& P, in
                 const int mid = (lo + hi) >> 1;
                 if (L.pelo[mid] <= i) lo = mid; else hi = mid;
             }
-            const int e = i + 2 * H * lo + H;
-            ts.e[k] = e;
+            ts.e[k] = i + 2 * H * lo + H;
             const int64_t x = t.lo + i;
-            ts.x[k] = x;
+#pragma unroll
             for (int f = 0; f < F; ++f) {
                 ts.uh[k][f] = st[f * N + x];
                 ts.ul[k][f] = use_lo ? stlo[f * N + x] : 0.f;
             }
             if (stage_io) {
                 const View<LR> kb{(LR*)P.kbuf, P.kbuf_len};
-                for (int s = 0; s < s0; ++s)
-                    for (int f = 0; f < F; ++f) ts.K[s][k][f] = kb[((int64_t)s * F + f) * N + x];
-            }
-            if (first) {   // stage-0 quantities of the own point
-                if constexpr (C::HILO) {
-                    L.g[0][e] = ts.uh[k][0];
-                    L.glo[e] = ts.ul[k][0];
-                } else {
-                    Q q[F];
-                    for (int f = 0; f < F; ++f) {
-                        if constexpr (C::F32) q[f] = (Q)ts.uh[k][f] + (Q)ts.ul[k][f];
-                        else q[f] = (Q)ts.uh[k][f];
-                    }
-                    put_quant<C>(L, P, e, q);
-                }
+#pragma unroll
+                for (int s = 0; s < S; ++s)
+                    if (s < s0)
+#pragma unroll
+                        for (int f = 0; f < F; ++f) ts.K[s][k][f] = kb[((int64_t)s * F + f) * N + x];
             }
         }
-        if (!first) return;
-        for (int idx = tid; idx < (t.npe + 1) * WL; idx += nth) {
-            const int b = idx / WL, w = idx % WL;
-            const int64_t x = wrapi(t.lo + L.pelo[b] - (int64_t)S * H + w, N);
-            const int64_t wp = (int64_t)b * WL + w;
-            const int64_t e = L.EXM + wp;
-            Q q[F];
-            for (int f = 0; f < F; ++f) {
-                const LR h = st[f * N + x];
-                const float l = use_lo ? stlo[f * N + x] : 0.f;
-                L.wu[f][wp] = h;
-                if constexpr (C::F32) {
-                    L.wulo[f][wp] = l;
-                    L.wq[f][wp] = l;
-                } else {
-                    L.wq[f][wp] = h;
-                }
-                if constexpr (C::F32) q[f] = (Q)h + (Q)l;
-                else q[f] = (Q)h;
-            }
-            if constexpr (C::HILO) {
-                L.g[0][e] = L.wu[0][wp];
-                L.glo[e] = L.wq[0][wp];
-            } else {
-                put_quant<C>(L, P, e, q);
-            }
-            const int h2 = w - (S - 1) * H;
-            if (h2 >= 0 && h2 < 2 * H) {
-                for (int f = 0; f < F; ++f) {
-                    L.SN[((int64_t)(b * S + 0) * 2 * H + h2) * F + f] = L.wq[f][wp];
-                    if constexpr (C::F32) L.SNhi[((int64_t)b * 2 * H + h2) * F + f] = L.wu[f][wp];
-                }
-            }
-        }
-    });
-    rt.sync();
-
-    // ---- P2: synchronous stages on the boundary windows -----------------------------
-    if (first) {
-        for (int s = 0; s + 1 < S; ++s) {
-            const int rlo = (s + 1) * H, rhi = WL - (s + 1) * H;   // R_s valid on [rlo, rhi)
-            if constexpr (C::WENO) {
-                rt.each([&](int tid, TS<C>&) {
-                    const int ni = rhi - rlo + 1;                   // interfaces rlo-1 .. rhi-1
-                    for (int idx = tid; idx < (t.npe + 1) * ni; idx += nth) {
-                        const int b = idx / ni, j = rlo - 1 + idx % ni;
-                        iface_flux<C>(L, P, L.EXM + (int64_t)b * WL + j);
-                    }
-                });
-                rt.sync();
-            }
-            rt.each([&](int tid, TS<C>&) {
-                const int nr = rhi - rlo;
-                for (int idx = tid; idx < (t.npe + 1) * nr; idx += nth) {
-                    const int b = idx / nr, w = rlo + idx % nr;
-                    const int64_t wp = (int64_t)b * WL + w;
-                    Q q[F];
-                    for (int f = 0; f < F; ++f) {
-                        if constexpr (C::F32) q[f] = (Q)L.wu[f][wp] + (Q)L.wq[f][wp];
-                        else q[f] = (Q)L.wq[f][wp];
-                    }
-                    LR K[F];
-                    rhs_at<C>(L, P, L.EXM + wp, q, K);
-                    for (int f = 0; f < F; ++f) L.wR[s][f][wp] = K[f];
-                }
-            });
-            rt.sync();
-            rt.each([&](int tid, TS<C>&) {
-                const int nr = rhi - rlo;
-                for (int idx = tid; idx < (t.npe + 1) * nr; idx += nth) {
-                    const int b = idx / nr, w = rlo + idx % nr;
-                    const int64_t wp = (int64_t)b * WL + w;
-                    const int64_t e = L.EXM + wp;
-                    Q q[F];
-                    for (int f = 0; f < F; ++f) {
-                        LR acc = LR(P.a[s + 1][0]) * L.wR[0][f][wp];
-                        for (int i = 1; i <= s; ++i) acc += LR(P.a[s + 1][i]) * L.wR[i][f][wp];
-                        if constexpr (C::F32) {
-                            const float lo = L.wulo[f][wp] + float(P.dt) * acc;
-                            L.wq[f][wp] = lo;
-                            q[f] = (Q)L.wu[f][wp] + (Q)lo;
-                        } else {
-                            const LR v = L.wu[f][wp] + LR(P.dt) * acc;
-                            L.wq[f][wp] = v;
-                            q[f] = (Q)v;
-                        }
-                    }
-                    if constexpr (C::HILO) {
-                        L.g[0][e] = L.wu[0][wp];
-                        L.glo[e] = L.wq[0][wp];
-                    } else {
-                        put_quant<C>(L, P, e, q);
-                    }
-                    const int h2 = w - (S - 1) * H;
-                    if (h2 >= 0 && h2 < 2 * H)
-                        for (int f = 0; f < F; ++f)
-                            L.SN[((int64_t)(b * S + s + 1) * 2 * H + h2) * F + f] = L.wq[f][wp];
-                }
-            });
-            rt.sync();
-        }
-    }
-
-    // ---- P3: write level-n strips, gather the delayed strips ------------------------
-    rt.each([&](int tid, TS<C>&) {
-        const int nrec = S * H * F;
+        // quantities of V(s0) at the own points
+        static_for<0, S>([&](auto sc) {
+            if (decltype(sc)::value != s0) return;
+#pragma unroll
+            for (int k = 0; k < PPT; ++k)
+                if (ts.e[k] >= 0) own_quant(ts, k, sc);
+        });
         if (first) {
-            for (int idx = tid; idx < 2 * t.npe * nrec; idx += nth) {
-                const int side_idx = idx / nrec, r = idx % nrec;
-                const int k = side_idx >> 1, side = side_idx & 1;
-                const int s = r / (H * F), h = (r / F) % H, f = r % F;
-                const int b = k + side, h2 = side * H + h;
-                unsigned char* rec = record_ptr<C>(P, n, t.pe0 + k, side);
-                const LR v = L.SN[((int64_t)(b * S + s) * 2 * H + h2) * F + f];
-                if constexpr (C::F32) {
-                    float* rf = (float*)rec;
-                    rf[H * F + (s * H + h) * F + f] = v;
-                    if (s == 0) rf[h * F + f] = L.SNhi[((int64_t)b * 2 * H + h2) * F + f];
+            for (int idx = tid; idx < (t.npe + 1) * WL; idx += nth) {
+                const int b = idx / WL, w = idx - b * WL;
+                const int64_t x = wrapi(t.lo + L.pelo[b] - (int64_t)S * H + w, N);
+                const int wp = b * WL + w;
+                Q q[F];
+                LR hv[F];
+                float lv[F];
+#pragma unroll
+                for (int f = 0; f < F; ++f) {
+                    hv[f] = st[f * N + x];
+                    lv[f] = use_lo ? stlo[f * N + x] : 0.f;
+                    L.wu[f][wp] = hv[f];
+                    if constexpr (C::F32) {
+                        L.wulo[f][wp] = lv[f];
+                        L.wq[0][f][wp] = lv[f];
+                        q[f] = (Q)hv[f] + (Q)lv[f];
+                    } else {
+                        L.wq[0][f][wp] = hv[f];
+                        q[f] = (Q)hv[f];
+                    }
+                    strip_out(b, w, 0, f, C::F32 ? (LR)lv[f] : hv[f], (float)hv[f]);
+                }
+                if constexpr (C::HILO) {
+                    L.win[0].g[0][wp] = hv[0];
+                    L.win[0].glo[wp] = lv[0];
                 } else {
-                    ((double*)rec)[(s * H + h) * F + f] = v;
+                    put_quant<C>(L.win[0], P, wp, q);
                 }
             }
         }
+        // delayed strips (and level n in per-stage mode) from the ring
+        const int nrec = S * H * F;
         const int per = J * nrec;
         for (int idx = tid; idx < 2 * t.npe * per; idx += nth) {
-            const int side_idx = idx / per, r = idx % per;
-            const int l = r / nrec, rr = r % nrec;
+            const int side_idx = idx / per, r = idx - side_idx * per;
+            const int l = r / nrec, rr = r - l * nrec;
             const int s = rr / (H * F), h = (rr / F) % H, f = rr % F;
             const int ke = L.keff[side_idx];
-            const int jeff = ke == 0 ? 1 : J;
-            if (l >= jeff) continue;
+            if (ke == 0 && (first || l > 0)) continue;   // from the window / weight 0
             const int k = side_idx >> 1, side = side_idx & 1;
             const int64_t m = n - ke - l;
-            const int64_t so = (int64_t)side_idx * L.SOREC + ((int64_t)(l * S + s) * H + h) * F + f;
-            const int64_t sohi = (((int64_t)side_idx * L.jmax + l) * H + h) * F + f;
-            if (m == n && first) {
-                const int b = k + side, h2 = side * H + h;
-                L.SO[so] = L.SN[((int64_t)(b * S + s) * 2 * H + h2) * F + f];
-                if constexpr (C::F32)
-                    if (s == 0) L.SOhi[sohi] = L.SNhi[((int64_t)b * 2 * H + h2) * F + f];
+            const int so = side_idx * L.SOREC + ((l * S + s) * H + h) * F + f;
+            const unsigned char* rec = record_ptr<C>(P, m, t.pe0 + k, side);
+            if constexpr (C::F32) {
+                const float* rf = (const float*)rec;
+                L.SO[so] = rf[ring_lo_off<C>(s, h, f)];
+                if (s == 0) L.SOhi[((side_idx * L.jmax + l) * H + h) * F + f] = rf[h * F + f];
             } else {
-                const unsigned char* rec = record_ptr<C>(P, m, t.pe0 + k, side);
-                if constexpr (C::F32) {
-                    const float* rf = (const float*)rec;
-                    L.SO[so] = rf[H * F + (s * H + h) * F + f];
-                    if (s == 0) L.SOhi[sohi] = rf[h * F + f];
-                } else {
-                    L.SO[so] = ((const double*)rec)[(s * H + h) * F + f];
-                }
+                L.SO[so] = ((const double*)rec)[((int64_t)s * H + h) * F + f];
             }
         }
     });
     rt.sync();
 
-    // ---- P4: the stages --------------------------------------------------------------
-    for (int s = s0; s <= s1; ++s) {
-        rt.each([&](int tid, TS<C>& ts) {
-            // own stage state V(s) = u^n + dt sum_{i<s} a_si K_i
-            if (s > 0 && (s > s0 || !first)) {
-                for (int k = 0; k < PPT; ++k) {
-                    const int e = ts.e[k];
-                    if (e < 0) continue;
-                    Q q[F];
-                    float vlo0 = 0.f;
-                    for (int f = 0; f < F; ++f) {
-                        LR acc = LR(P.a[s][0]) * ts.K[0][k][f];
-                        for (int i = 1; i < s; ++i) acc += LR(P.a[s][i]) * ts.K[i][k][f];
-                        if constexpr (C::F32) {
-                            const float lo = ts.ul[k][f] + float(P.dt) * acc;
-                            if (f == 0) vlo0 = lo;
-                            q[f] = (Q)ts.uh[k][f] + (Q)lo;
-                        } else {
-                            q[f] = ts.uh[k][f] + LR(P.dt) * acc;
-                        }
-                    }
-                    if constexpr (C::HILO) {
-                        L.g[0][e] = ts.uh[k][0];
-                        L.glo[e] = vlo0;
-                    } else {
-                        put_quant<C>(L, P, e, q);
-                    }
-                }
-            }
-            // halo fill: time-extrapolated synchronous stage s of the delayed levels
-            for (int idx = tid; idx < 2 * t.npe * H; idx += nth) {
-                const int side_idx = idx / H, h = idx % H;
-                const int k = side_idx >> 1, side = side_idx & 1;
-                const int ke = L.keff[side_idx];
-                const int jeff = ke == 0 ? 1 : J;
-                double w[MAXJ];
-                lagrange_weights(jeff, ke, w);
-                const int np = L.pelo[k + 1] - L.pelo[k];
-                const int64_t ebase = (int64_t)L.pelo[k] + 2 * H * k;
-                const int64_t e = side == 0 ? ebase + h : ebase + H + np + h;
-                auto sov = [&](int l, int f) -> LR {
-                    return L.SO[(int64_t)side_idx * L.SOREC + ((int64_t)(l * S + s) * H + h) * F + f];
-                };
-                auto sohi = [&](int l, int f) -> float {
-                    return L.SOhi[(((int64_t)side_idx * L.jmax + l) * H + h) * F + f];
-                };
-                if constexpr (C::HILO) {
-                    const float h0 = sohi(0, 0), l0 = sov(0, 0);
-                    float lo = l0;
-                    for (int l = 1; l < jeff; ++l)
-                        lo += float(w[l]) * ((sohi(l, 0) - h0) + (sov(l, 0) - l0));
-                    L.g[0][e] = h0;
-                    L.glo[e] = lo;
-                } else {
-                    constexpr int NQ = C::NQ;
-                    Q gl[NQ], g0[NQ], acc[NQ];
-                    for (int j = 0; j < NQ; ++j) acc[j] = g0[j] = Q(0);
-                    Q lam0 = Q(0), laml = Q(0);
-                    for (int l = 0; l < jeff; ++l) {
-                        Q q[F];
-                        for (int f = 0; f < F; ++f) {
-                            if constexpr (C::F32) q[f] = (Q)sohi(l, f) + (Q)sov(l, f);
-                            else q[f] = (Q)sov(l, f);
-                        }
-                        quant_values<C>(P, q, gl, laml);
-                        if (l == 0) {
-                            lam0 = laml;
-                            for (int j = 0; j < NQ; ++j) {
-                                g0[j] = gl[j];
-                                acc[j] = C::F32 ? gl[j] : Q(w[0]) * gl[j];
-                            }
-                        } else {
-                            for (int j = 0; j < NQ; ++j) {
-                                if constexpr (C::F32) acc[j] += Q(w[l]) * (gl[j] - g0[j]);
-                                else acc[j] += Q(w[l]) * gl[j];
-                            }
-                        }
-                    }
-                    for (int j = 0; j < NQ; ++j) L.g[j][e] = (LR)acc[j];
-                    if constexpr (C::WENO) L.lam[e] = (LR)lam0;
-                }
-            }
-        });
-        rt.sync();
-        if constexpr (C::WENO) {
+    // ---- the stages ----------------------------------------------------------------
+    static_for<0, S>([&](auto sc) {
+        constexpr int s = decltype(sc)::value;
+        const bool own_active = s >= s0 && s <= s1;
+        const bool win_active = first && s + 1 < S;
+        if (!own_active && !win_active) return;
+        const QV<C>& Wc = L.win[s & 1];
+        const QV<C>& Wn = L.win[(s + 1) & 1];
+
+        // A: own quantities of V(s), halo fill of stage s
+        if (own_active) {
             rt.each([&](int tid, TS<C>& ts) {
-                for (int k = 0; k < PPT; ++k) {
-                    const int e = ts.e[k];
-                    if (e < 0) continue;
-                    iface_flux<C>(L, P, e);                 // right interface of the point
-                    const int i = (int)(ts.x[k] - t.lo);
-                    // left interface of the PE's first point
-                    int lo = 0, hi = t.npe;
-                    while (hi - lo > 1) {
-                        const int mid = (lo + hi) >> 1;
-                        if (L.pelo[mid] <= i) lo = mid; else hi = mid;
+                if (s > s0) {
+#pragma unroll
+                    for (int k = 0; k < PPT; ++k)
+                        if (ts.e[k] >= 0) own_quant(ts, k, sc);
+                }
+                for (int idx = tid; idx < 2 * t.npe * H; idx += nth) {
+                    const int side_idx = idx / H, h = idx - side_idx * H;
+                    const int k = side_idx >> 1, side = side_idx & 1;
+                    const int ke = L.keff[side_idx];
+                    const int np = L.pelo[k + 1] - L.pelo[k];
+                    const int ebase = L.pelo[k] + 2 * H * k;
+                    const int e = side == 0 ? ebase + h : ebase + H + np + h;
+                    if (ke == 0 && first) {
+                        // synchronous stage s of level n: the window's value at the halo point
+                        const int wp = (k + side) * WL + (S - 1) * H + side * H + h;
+#pragma unroll
+                        for (int j = 0; j < NQ; ++j) L.main.g[j][e] = Wc.g[j][wp];
+                        if constexpr (C::HILO) L.main.glo[e] = Wc.glo[wp];
+                        if constexpr (C::WENO) L.main.lam[e] = Wc.lam[wp];
+                        continue;
                     }
-                    if (L.pelo[lo] == i) iface_flux<C>(L, P, e - 1);
+                    const int jeff = ke == 0 ? 1 : J;
+                    double w[JM];
+                    lagrange_weights(jeff, ke, w);
+                    const int sob = side_idx * L.SOREC;
+                    const int sohb = side_idx * L.jmax;
+                    if constexpr (C::HILO) {
+                        const float h0 = L.SOhi[((sohb + 0) * H + h) * F];
+                        const float l0 = L.SO[sob + ((0 * S + s) * H + h) * F];
+                        float lo = l0;
+#pragma unroll
+                        for (int l = 1; l < JM; ++l) {
+                            if (l >= jeff) continue;
+                            const float hl = L.SOhi[((sohb + l) * H + h) * F];
+                            const float ll = L.SO[sob + ((l * S + s) * H + h) * F];
+                            lo += float(w[l]) * ((hl - h0) + (ll - l0));
+                        }
+                        L.main.g[0][e] = h0;
+                        L.main.glo[e] = lo;
+                    } else {
+                        Q gl[NQ], g0[NQ], acc[NQ];
+                        Q lam0 = Q(0), laml = Q(0);
+#pragma unroll
+                        for (int l = 0; l < JM; ++l) {
+                            if (l >= jeff) continue;
+                            Q q[F];
+#pragma unroll
+                            for (int f = 0; f < F; ++f) {
+                                const LR v = L.SO[sob + ((l * S + s) * H + h) * F + f];
+                                if constexpr (C::F32) q[f] = (Q)L.SOhi[((sohb + l) * H + h) * F + f] + (Q)v;
+                                else q[f] = (Q)v;
+                            }
+                            quant_values<C>(P, q, gl, laml);
+                            if (l == 0) {
+                                lam0 = laml;
+#pragma unroll
+                                for (int j = 0; j < NQ; ++j) {
+                                    g0[j] = gl[j];
+                                    acc[j] = C::F32 ? gl[j] : Q(w[0]) * gl[j];
+                                }
+                            } else {
+#pragma unroll
+                                for (int j = 0; j < NQ; ++j) {
+                                    if constexpr (C::F32) acc[j] += Q(w[l]) * (gl[j] - g0[j]);
+                                    else acc[j] += Q(w[l]) * gl[j];
+                                }
+                            }
+                        }
+#pragma unroll
+                        for (int j = 0; j < NQ; ++j) L.main.g[j][e] = (LR)acc[j];
+                        if constexpr (C::WENO) L.main.lam[e] = (LR)lam0;
+                    }
                 }
             });
             rt.sync();
         }
-        rt.each([&](int tid, TS<C>& ts) {
-            for (int k = 0; k < PPT; ++k) {
-                const int e = ts.e[k];
-                if (e < 0) continue;
-                Q q[F];
-                for (int f = 0; f < F; ++f) {
-                    if (s == 0) {
-                        if constexpr (C::F32) q[f] = (Q)ts.uh[k][f] + (Q)ts.ul[k][f];
-                        else q[f] = (Q)ts.uh[k][f];
-                    } else {
-                        LR acc = LR(P.a[s][0]) * ts.K[0][k][f];
-                        for (int i = 1; i < s; ++i) acc += LR(P.a[s][i]) * ts.K[i][k][f];
-                        if constexpr (C::F32) q[f] = (Q)ts.uh[k][f] + (Q)(ts.ul[k][f] + float(P.dt) * acc);
-                        else q[f] = ts.uh[k][f] + LR(P.dt) * acc;
+
+        // B1 (WENO): interface fluxes
+        if constexpr (C::WENO) {
+            rt.each([&](int tid, TS<C>& ts) {
+                if (own_active) {
+#pragma unroll
+                    for (int k = 0; k < PPT; ++k) {
+                        const int e = ts.e[k];
+                        if (e < 0) continue;
+                        iface_flux<C>(L.main, P, e);              // right interface of the point
+                        // left interface of the PE's first point: its left neighbour is a halo slot
+                        const int i = tid + k * nth;
+                        int lo = 0, hi = t.npe;
+                        while (hi - lo > 1) {
+                            const int mid = (lo + hi) >> 1;
+                            if (L.pelo[mid] <= i) lo = mid; else hi = mid;
+                        }
+                        if (L.pelo[lo] == i) iface_flux<C>(L.main, P, e - 1);
                     }
                 }
-                LR K[F];
-                rhs_at<C>(L, P, e, q, K);
-                for (int f = 0; f < F; ++f) ts.K[s][k][f] = K[f];
+                if (win_active) {
+                    const int rlo = (s + 1) * H, rhi = WL - (s + 1) * H;
+                    const int ni = rhi - rlo + 1;                 // interfaces rlo-1 .. rhi-1
+                    for (int idx = tid; idx < (t.npe + 1) * ni; idx += nth) {
+                        const int b = idx / ni, j = rlo - 1 + (idx - b * ni);
+                        iface_flux<C>(Wc, P, b * WL + j);
+                    }
+                }
+            });
+            rt.sync();
+        }
+
+        // B2: K_s at own points; R_s and the synchronous stage s+1 on the windows
+        rt.each([&](int tid, TS<C>& ts) {
+            if (own_active) {
+#pragma unroll
+                for (int k = 0; k < PPT; ++k) {
+                    const int e = ts.e[k];
+                    if (e < 0) continue;
+                    Q q[F];
+                    float vlo;
+#pragma unroll
+                    for (int f = 0; f < F; ++f) q[f] = own_state(ts, k, f, sc, vlo);
+                    LR K[F];
+                    rhs_at<C>(L.main, P, e, q, K);
+#pragma unroll
+                    for (int f = 0; f < F; ++f) ts.K[s][k][f] = K[f];
+                }
+            }
+            if (win_active) {
+                const int rlo = (s + 1) * H, rhi = WL - (s + 1) * H;
+                const int nr = rhi - rlo;
+                for (int idx = tid; idx < (t.npe + 1) * nr; idx += nth) {
+                    const int b = idx / nr, w = rlo + (idx - b * nr);
+                    const int wp = b * WL + w;
+                    Q q[F];
+#pragma unroll
+                    for (int f = 0; f < F; ++f) {
+                        if constexpr (C::F32) q[f] = (Q)L.wu[f][wp] + (Q)L.wq[s & 1][f][wp];
+                        else q[f] = (Q)L.wq[s & 1][f][wp];
+                    }
+                    LR K[F];
+                    rhs_at<C>(Wc, P, wp, q, K);
+                    Q qn[F];
+                    LR hv[F];
+                    float lvn[F];
+#pragma unroll
+                    for (int f = 0; f < F; ++f) {
+                        L.wR[s][f][wp] = K[f];
+                        LR acc = LR(P.a[s + 1][0]) * L.wR[0][f][wp];
+#pragma unroll
+                        for (int i = 1; i <= s; ++i) acc += LR(P.a[s + 1][i]) * L.wR[i][f][wp];
+                        hv[f] = L.wu[f][wp];
+                        if constexpr (C::F32) {
+                            const float lo = L.wulo[f][wp] + float(dt) * acc;
+                            lvn[f] = lo;
+                            L.wq[(s + 1) & 1][f][wp] = lo;
+                            qn[f] = (Q)hv[f] + (Q)lo;
+                            strip_out(b, w, s + 1, f, lo, 0.f);
+                        } else {
+                            const LR v = hv[f] + dt * acc;
+                            lvn[f] = 0.f;
+                            L.wq[(s + 1) & 1][f][wp] = v;
+                            qn[f] = (Q)v;
+                            strip_out(b, w, s + 1, f, v, 0.f);
+                        }
+                    }
+                    if constexpr (C::HILO) {
+                        Wn.g[0][wp] = hv[0];
+                        Wn.glo[wp] = lvn[0];
+                    } else {
+                        put_quant<C>(Wn, P, wp, qn);
+                    }
+                }
             }
         });
         rt.sync();
-    }
+    });
 
     // ---- P5: the update (or the stage output of the per-stage entry point) ----------
     rt.each([&](int tid, TS<C>& ts) {
-        (void)tid;
+#pragma unroll
         for (int k = 0; k < PPT; ++k) {
             if (ts.e[k] < 0) continue;
-            const int64_t x = ts.x[k];
+            const int64_t x = t.lo + tid + k * nth;
             if (s1 < S - 1) {
                 const View<LR> kb{(LR*)P.kbuf, P.kbuf_len};
-                for (int f = 0; f < F; ++f) kb[((int64_t)s1 * F + f) * N + x] = ts.K[s1][k][f];
+                static_for<0, S>([&](auto sc) {
+                    constexpr int s = decltype(sc)::value;
+                    if (s != s1) return;
+#pragma unroll
+                    for (int f = 0; f < F; ++f) kb[((int64_t)s * F + f) * N + x] = ts.K[s][k][f];
+                });
                 continue;
             }
             const View<LR> dst = st_view<C>(P, nxt);
             const View<float> dlo = lo_view(P, nxt, C::F32);
+#pragma unroll
             for (int f = 0; f < F; ++f) {
                 LR acc = LR(P.bw[0]) * ts.K[0][k][f];
+#pragma unroll
                 for (int s = 1; s < S; ++s) acc += LR(P.bw[s]) * ts.K[s][k][f];
                 if constexpr (C::F32) {
                     // compensated update: (hi, lo) + dt*acc, TwoSum of hi and (lo + dt*acc)
                     const float hi = ts.uh[k][f];
-                    const float tt = ts.ul[k][f] + float(P.dt) * acc;
+                    const float tt = ts.ul[k][f] + float(dt) * acc;
                     const float sum = hi + tt;
                     const float bb = sum - hi;
                     const float err = (hi - (sum - bb)) + (tt - bb);
                     dst[f * N + x] = sum;
                     if (P.keep_lo) dlo[f * N + x] = err;
                 } else {
-                    dst[f * N + x] = ts.uh[k][f] + LR(P.dt) * acc;
+                    dst[f * N + x] = ts.uh[k][f] + dt * acc;
                 }
             }
         }

@@ -1,16 +1,21 @@
-// at_variants.hpp -- the compiled set of tile-kernel variants (kind, halo width
-// H, RK stages S, FP32 form).  One X-macro list shared by the kernels, the
-// planner's size queries and the CPU emulation.
+// at_variants.hpp -- the compiled set of tile-kernel variants: kind, halo width
+// H, RK stages S, FP32 form, and points per thread (PPT; a tile holds at most
+// 256 * PPT points, so each variant comes in a small and a large tile class).
+// One X-macro list shared by the kernels, the planner and the CPU emulation.
 #pragma once
 #include "at_tile.hpp"
 
 namespace atk {
-constexpr int ppt_c(int kind) { return (kind == K_ADR || kind == K_WSCAL) ? 8 : 4; }
+// points-per-thread classes of each kind: small (default tiles) and large (big PEs)
+constexpr int ppt_small(int kind) { return (kind == K_ADR || kind == K_WSCAL) ? 4 : 2; }
+constexpr int ppt_large(int kind) { return (kind == K_ADR || kind == K_WSCAL) ? 8 : 4; }
 }  // namespace atk
 
+#define AT_VARIANTS_P(X, K, H, S, F32) X(K, H, S, F32, atk::ppt_small(K)) X(K, H, S, F32, atk::ppt_large(K))
 #define AT_VARIANTS_SF(X, K, H) \
-    X(K, H, 1, 0) X(K, H, 2, 0) X(K, H, 3, 0) X(K, H, 4, 0) \
-    X(K, H, 1, 1) X(K, H, 2, 1) X(K, H, 3, 1) X(K, H, 4, 1)
+    AT_VARIANTS_P(X, K, H, 1, 0) AT_VARIANTS_P(X, K, H, 2, 0) AT_VARIANTS_P(X, K, H, 3, 0) \
+    AT_VARIANTS_P(X, K, H, 4, 0) AT_VARIANTS_P(X, K, H, 1, 1) AT_VARIANTS_P(X, K, H, 2, 1) \
+    AT_VARIANTS_P(X, K, H, 3, 1) AT_VARIANTS_P(X, K, H, 4, 1)
 
 #define AT_VARIANTS_ADR(X) AT_VARIANTS_SF(X, atk::K_ADR, 1) AT_VARIANTS_SF(X, atk::K_ADR, 2) \
     AT_VARIANTS_SF(X, atk::K_ADR, 4)
@@ -22,4 +27,4 @@ constexpr int ppt_c(int kind) { return (kind == K_ADR || kind == K_WSCAL) ? 8 : 
 #define AT_VARIANTS(X) AT_VARIANTS_ADR(X) AT_VARIANTS_RNS(X) AT_VARIANTS_WSCAL(X) \
     AT_VARIANTS_EUL(X) AT_VARIANTS_REUL(X)
 
-#define AT_CFG(K, H, S, F32) atk::Cfg<K, H, S, (F32) != 0, atk::ppt_c(K)>
+#define AT_CFG(K, H, S, F32, PPT) atk::Cfg<K, H, S, (F32) != 0, PPT>
