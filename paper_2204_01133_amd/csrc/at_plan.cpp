@@ -172,7 +172,7 @@ int make_plan(const at_problem_desc* probs, int n_probs, const at_run_opts* opts
 
     // ---- tiles: whole PEs packed up to the tile target and the LDS budget; a PE
     //      larger than a small tile gets a tile of the large points-per-thread class ----
-    const int64_t lds_budget = 48 * 1024;
+    const int64_t lds_budget = 30 * 1024;     // ~5 workgroups per CU
     const int64_t lds_hard = 160 * 1024;
     std::vector<std::vector<Tile>> small(n_probs), large(n_probs);
     for (int b = 0; b < n_probs; ++b) {
@@ -268,13 +268,15 @@ int make_plan(const at_problem_desc* probs, int n_probs, const at_run_opts* opts
         std::stable_sort(ts.begin(), ts.end(), [&](const Tile& x, const Tile& y) { return cost(x) > cost(y); });
         g.t0 = (int)plan.tiles_bt.size();
         g.ntiles = (int)ts.size();
+        g.lds_bytes = 0;
         for (const Tile& t : ts) {
             g.npts_max = std::max(g.npts_max, t.npts);
             g.npe_max = std::max(g.npe_max, t.npe);
+            int64_t lds, rec;
+            variant_sizes(g.key, t.npts, t.npe, g.jmax, &lds, &rec);   // layouts are per tile
+            g.lds_bytes = std::max(g.lds_bytes, lds);
         }
         plan.tiles_bt.insert(plan.tiles_bt.end(), ts.begin(), ts.end());
-        int64_t rec;
-        variant_sizes(g.key, g.npts_max, g.npe_max, g.jmax, &g.lds_bytes, &rec);
         if (g.lds_bytes > lds_hard) {
             err = fmt("kernel group needs %lld bytes of LDS", g.lds_bytes);
             return AT_EUNSUPPORTED;

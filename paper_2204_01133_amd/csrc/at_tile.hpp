@@ -156,8 +156,9 @@ struct Layout {
         o_glo = o;   o += C::HILO ? align16(EXM * 4) : 0;
         o_lam = o;   o += C::WENO ? align16(EXM * sl) : 0;
         o_flux = o;  o += C::WENO ? align16(C::F * EXM * sl) : 0;
-        o_gw = o;    o += align16(2 * C::NQ * EXW * sl);
-        o_gwlo = o;  o += C::HILO ? align16(2 * EXW * 4) : 0;
+        // the scalar FD kind's window quantities are its window state (aliased below)
+        o_gw = o;    o += C::KIND == K_ADR ? 0 : align16(2 * C::NQ * EXW * sl);
+        o_gwlo = o;
         o_lamw = o;  o += C::WENO ? align16(2 * EXW * sl) : 0;
         o_fluxw = o; o += C::WENO ? align16(C::F * EXW * sl) : 0;
         o_wu = o;    o += align16(C::F * EXW * sl);
@@ -340,6 +341,17 @@ struct Lds {
                 wq[par][f] = View<L>{(L*)(base + Lo.o_wq) + (par * C::F + f) * nw, nw};
             for (int r = 0; r < SR; ++r)
                 wR[r][f] = View<L>{(L*)(base + Lo.o_wR) + (r * C::F + f) * nw, nw};
+        }
+        if constexpr (C::KIND == K_ADR) {
+            // window quantity g = stage state: FP64 value, or FP32 hi (= raw hi) with lo
+            for (int par = 0; par < 2; ++par) {
+                if constexpr (C::HILO) {
+                    win[par].g[0] = wu[0];
+                    win[par].glo = View<float>{(float*)wq[par][0].p, nw};
+                } else {
+                    win[par].g[0] = wq[par][0];
+                }
+            }
         }
         SO = View<L>{(L*)(base + Lo.o_SO), 2 * (int64_t)npe_max * Lo.SOREC};
         SOhi = View<float>{(float*)(base + Lo.o_SOhi), C::F32 ? 2 * (int64_t)npe_max * jm * C::H * C::F : 0};
@@ -587,10 +599,12 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t, const ProbDev& P, in
     using Q = typename C::qreal;
     constexpr int F = C::F, H = C::H, S = C::S, PPT = C::PPT, WL = C::WL, NQ = C::NQ;
 
+    // LDS layout sized by this tile (the launch allocates the largest over its tiles)
     Layout<C> Lo;
-    Lo.init(a.npts_max, a.npe_max, a.jmax);
+    Lo.init(t.npts, t.npe, a.jmax);
+    AT_CHECK(Lo.total <= a.lds_bytes, "tile LDS", Lo.total, a.lds_bytes);
     Lds<C> L;
-    L.init(lds_base, Lo, a.npe_max, a.jmax);
+    L.init(lds_base, Lo, t.npe, a.jmax);
 
     const int nth = rt.nthreads();
     const int s0 = a.s_begin, s1 = a.s_end;
