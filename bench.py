@@ -116,6 +116,8 @@ def main():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--only-headline", action="store_true",
+                    help="time only the headline FP32 batched form (profiler runs)")
     ap.add_argument("--sample", type=int, default=64, help="problems in the oracle sample")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -140,6 +142,12 @@ def main():
     value = total_pts * S * K / t32
     ms_step = t32 * 1000.0 / K
     achieved = bytes32["total"] / (t32 / K) / 1e9
+
+    if args.only_headline:
+        line = {"metric": "grid-point RK-stage updates/s", "value": value, "ms_per_step": ms_step,
+                "steps": K, "warmup": Wm, "hbm_gbs": achieved, "bytes_per_launch": bytes32["total"]}
+        print(json.dumps(line))
+        return
 
     # FP64 batched, FP64 plain (one launch per problem, fewer steps: launch bound)
     prs64 = [p.replace(precision="fp64") for p in base]

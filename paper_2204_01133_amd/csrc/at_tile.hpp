@@ -141,8 +141,9 @@ AT_HD AT_FI int64_t align16(int64_t b) { return (b + 15) & ~int64_t(15); }
 template <class C>
 struct Layout {
     int64_t EXM, EXW, NW, SOREC;
+    int64_t EXR;   // raw staging range [lo - S*H, lo + npts + S*H)
     int64_t o_g, o_glo, o_lam, o_flux, o_gw, o_gwlo, o_lamw, o_fluxw, o_wu, o_wulo, o_wq, o_wR,
-        o_SO, o_SOhi, o_pelo, o_keff, total;
+        o_SO, o_SOhi, o_pelo, o_keff, o_rh, o_rl, total;
     AT_HD void init(int npts_max, int npe_max, int jmax) {
         using L = typename C::lreal;
         const int64_t sl = (int64_t)sizeof(L);
@@ -150,6 +151,7 @@ struct Layout {
         NW = npe_max + 1;
         EXW = NW * C::WL;
         SOREC = (int64_t)jmax * C::S * C::H * C::F;  // per PE side
+        EXR = npts_max + 2 * C::S * C::H;
         const int64_t SR = C::S > 1 ? C::S - 1 : 1;
         int64_t o = 0;
         o_g = o;     o += align16(C::NQ * EXM * sl);
@@ -169,6 +171,8 @@ struct Layout {
         o_SOhi = o;  o += C::F32 ? align16(2 * (int64_t)npe_max * jmax * C::H * C::F * 4) : 0;
         o_pelo = o;  o += align16((npe_max + 1) * 4);
         o_keff = o;  o += align16(2 * (int64_t)npe_max * 4);
+        o_rh = o;    o += align16(C::F * EXR * sl);
+        o_rl = o;    o += C::F32 ? align16(C::F * EXR * 4) : 0;
         total = o;
     }
 };
@@ -317,6 +321,8 @@ struct Lds {
     View<L> SO;
     View<float> SOhi;
     View<int> pelo, keff;
+    View<L> rh[C::F];          // raw u^n (FP64 value / FP32 hi) on [lo - S*H, lo + npts + S*H)
+    View<float> rl[C::F];      // raw FP32 lo
     int EXM, EXW, SOREC, jmax;
     AT_HD void init(unsigned char* base, const Layout<C>& Lo, int npe_max, int jm) {
         EXM = (int)Lo.EXM; EXW = (int)Lo.EXW; SOREC = (int)Lo.SOREC; jmax = jm;
@@ -357,6 +363,10 @@ struct Lds {
         SOhi = View<float>{(float*)(base + Lo.o_SOhi), C::F32 ? 2 * (int64_t)npe_max * jm * C::H * C::F : 0};
         pelo = View<int>{(int*)(base + Lo.o_pelo), npe_max + 1};
         keff = View<int>{(int*)(base + Lo.o_keff), 2 * (int64_t)npe_max};
+        for (int f = 0; f < C::F; ++f) {
+            rh[f] = View<L>{(L*)(base + Lo.o_rh) + f * Lo.EXR, Lo.EXR};
+            rl[f] = View<float>{(float*)(base + Lo.o_rl) + f * Lo.EXR, C::F32 ? Lo.EXR : 0};
+        }
     }
 };
 
@@ -580,9 +590,10 @@ AT_HD AT_FI unsigned char* record_ptr(const ProbDev& P, int64_t level, int64_t p
 // ---------------------------------------------------------------------------
 // the tile step
 //
-//   P0  PE offsets, delays
-//   P1  own points (registers, stage-s0 quantities), boundary windows of level n
-//       (stage-0 quantities, ring records of stage 0), delayed strips -> LDS
+//   P1  every global read in one phase: the raw range [lo - S*H, lo + npts + S*H)
+//       of u^n, PE offsets, delays, delayed strips of the ring -> LDS
+//   P2  own points (registers, stage-s0 quantities), boundary windows of level n
+//       from the raw range (stage-0 quantities, ring records of stage 0)
 //   per stage s:  A  own quantities of V(s), halo fill (extrapolated strips, or
 //                    the window's synchronous stage s when the delay is 0)
 //                 B  [WENO: interface fluxes]  K_s at own points; R_s on the
@@ -643,43 +654,120 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t, const ProbDev& P, in
         }
     };
 
-    // ---- P0: PE offsets and delays ----------------------------------------------
-    rt.each([&](int tid, TS<C>&) {
+    // delay of PE (t.pe0 + k), side: drawn and effective (clamped to the held history)
+    auto delays_of = [&](int k, int side, int& kd) -> int {
+        const int64_t pe = t.pe0 + k;
+        if (P.ov && n >= P.ov_step0 && n < P.ov_step0 + P.ov_n) {
+            const int64_t oi = ((n - P.ov_step0) * P.p + pe) * 2 + side;
+            AT_CHECK(oi >= 0 && oi < P.ov_n * P.p * 2, "override", oi, P.ov_n * P.p * 2);
+            kd = P.ov[oi];
+        } else if (P.gran == G_PE) {
+            kd = draw_delay(P, n, pe, 0);
+        } else if (P.gran == G_PE_SIDE) {
+            kd = draw_delay(P, n, pe, side);
+        } else {
+            kd = draw_delay(P, n, side == 0 ? pe : (pe + 1 == P.p ? 0 : pe + 1), 0);
+        }
+        int ke;
+        if (P.mode == M_AT) {
+            ke = kd;
+            if ((int64_t)ke > n - (J - 1)) ke = (int)(n - (J - 1));
+            if (ke < 0) ke = 0;
+        } else if (P.mode == M_AS) {
+            ke = (int64_t)kd < n ? kd : (int)n;
+        } else {
+            ke = 0;
+        }
+        return ke;
+    };
+
+    // ---- P1: every global read of the tile in one phase -----------------------------
+    //   raw u^n on [lo - S*H, lo + npts + S*H) (own points and boundary windows),
+    //   PE offsets, delays, delayed strips of the ring, stage inputs (per-stage mode)
+    constexpr int SH = S * H;
+    rt.each([&](int tid, TS<C>& ts) {
+        const int nraw = t.npts + 2 * SH;
+        AT_CHECK(nraw <= nth * (PPT + 1), "raw range", nraw, nth * (PPT + 1));
+        {   // all loads first (registers), then the LDS stores
+            LR vh[PPT + 1][F];
+            float vl[PPT + 1][F];
+#pragma unroll
+            for (int k = 0; k <= PPT; ++k) {
+                const int r = tid + k * nth;
+                if (r >= nraw) continue;
+                int64_t x = t.lo - SH + r;
+                if (x < 0 || x >= N) x = wrapi(x, N);
+#pragma unroll
+                for (int f = 0; f < F; ++f) {
+                    vh[k][f] = st[f * N + x];
+                    vl[k][f] = use_lo ? stlo[f * N + x] : 0.f;
+                }
+            }
+#pragma unroll
+            for (int k = 0; k <= PPT; ++k) {
+                const int r = tid + k * nth;
+                if (r >= nraw) continue;
+#pragma unroll
+                for (int f = 0; f < F; ++f) {
+                    L.rh[f][r] = vh[k][f];
+                    if constexpr (C::F32) L.rl[f][r] = vl[k][f];
+                }
+            }
+        }
         for (int k = tid; k <= t.npe; k += nth) {
             const int64_t lo = ((int64_t)(t.pe0 + k) * N) / P.p;
             L.pelo[k] = (int)(lo - t.lo);
         }
-        for (int i = tid; i < 2 * t.npe; i += nth) {
-            const int k = i >> 1, side = i & 1;
-            const int64_t pe = t.pe0 + k;
+        constexpr int nrec = S * H * F;
+        for (int side_idx = tid; side_idx < 2 * t.npe; side_idx += nth) {
+            const int k = side_idx >> 1, side = side_idx & 1;
             int kd;
-            if (P.ov && n >= P.ov_step0 && n < P.ov_step0 + P.ov_n) {
-                const int64_t oi = ((n - P.ov_step0) * P.p + pe) * 2 + side;
-                AT_CHECK(oi >= 0 && oi < P.ov_n * P.p * 2, "override", oi, P.ov_n * P.p * 2);
-                kd = P.ov[oi];
-            } else if (P.gran == G_PE) {
-                kd = draw_delay(P, n, pe, 0);
-            } else if (P.gran == G_PE_SIDE) {
-                kd = draw_delay(P, n, pe, side);
-            } else {
-                kd = draw_delay(P, n, side == 0 ? pe : (pe + 1) % P.p, 0);
-            }
-            int ke;
-            if (P.mode == M_AT) {
-                ke = kd;
-                if ((int64_t)ke > n - (J - 1)) ke = (int)(n - (J - 1));
-                if (ke < 0) ke = 0;
-            } else if (P.mode == M_AS) {
-                ke = (int64_t)kd < n ? kd : (int)n;
-            } else {
-                ke = 0;
-            }
-            L.keff[i] = ke;
+            const int ke = delays_of(k, side, kd);
+            L.keff[side_idx] = ke;
             if ((a.flags & KF_LOG) && first && P.log_drawn) {
-                const int64_t li = (wrapi(n, P.log_cap) * P.p + pe) * 2 + side;
+                const int64_t li = (wrapi(n, P.log_cap) * P.p + t.pe0 + k) * 2 + side;
                 AT_CHECK(li >= 0 && li < P.log_cap * P.p * 2, "log", li, P.log_cap * P.p * 2);
                 P.log_drawn[li] = (uint8_t)kd;
                 P.log_eff[li] = (uint8_t)ke;
+            }
+            // delayed strips (and level n in per-stage mode) from the ring
+            const int jeff = ke == 0 ? (first ? 0 : 1) : J;
+#pragma unroll
+            for (int l = 0; l < JM; ++l) {
+                if (l >= jeff) continue;
+                const unsigned char* rec = record_ptr<C>(P, n - ke - l, t.pe0 + k, side);
+                const int sob = side_idx * L.SOREC + l * nrec;
+                LR v[nrec];
+                float vh[C::F32 ? H * F : 1];
+#pragma unroll
+                for (int r = 0; r < nrec; ++r) {
+                    if constexpr (C::F32) v[r] = ((const float*)rec)[H * F + r];
+                    else v[r] = ((const double*)rec)[r];
+                }
+                if constexpr (C::F32) {
+#pragma unroll
+                    for (int r = 0; r < H * F; ++r) vh[r] = ((const float*)rec)[r];
+                }
+#pragma unroll
+                for (int r = 0; r < nrec; ++r) L.SO[sob + r] = v[r];
+                if constexpr (C::F32) {
+#pragma unroll
+                    for (int r = 0; r < H * F; ++r) L.SOhi[(side_idx * L.jmax + l) * H * F + r] = vh[r];
+                }
+            }
+        }
+        if (stage_io) {
+            const View<LR> kb{(LR*)P.kbuf, P.kbuf_len};
+#pragma unroll
+            for (int k = 0; k < PPT; ++k) {
+                const int i = tid + k * nth;
+                if (i >= t.npts) continue;
+                const int64_t x = t.lo + i;
+#pragma unroll
+                for (int s = 0; s < S; ++s)
+                    if (s < s0)
+#pragma unroll
+                        for (int f = 0; f < F; ++f) ts.K[s][k][f] = kb[((int64_t)s * F + f) * N + x];
             }
         }
     });
@@ -720,7 +808,7 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t, const ProbDev& P, in
         }
     };
 
-    // ---- P1: own points, boundary windows, delayed strips ---------------------------
+    // ---- P2: own points and boundary windows from the staged raw range --------------
     rt.each([&](int tid, TS<C>& ts) {
 #pragma unroll
         for (int k = 0; k < PPT; ++k) {
@@ -733,19 +821,10 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t, const ProbDev& P, in
                 if (L.pelo[mid] <= i) lo = mid; else hi = mid;
             }
             ts.e[k] = i + 2 * H * lo + H;
-            const int64_t x = t.lo + i;
 #pragma unroll
             for (int f = 0; f < F; ++f) {
-                ts.uh[k][f] = st[f * N + x];
-                ts.ul[k][f] = use_lo ? stlo[f * N + x] : 0.f;
-            }
-            if (stage_io) {
-                const View<LR> kb{(LR*)P.kbuf, P.kbuf_len};
-#pragma unroll
-                for (int s = 0; s < S; ++s)
-                    if (s < s0)
-#pragma unroll
-                        for (int f = 0; f < F; ++f) ts.K[s][k][f] = kb[((int64_t)s * F + f) * N + x];
+                ts.uh[k][f] = L.rh[f][i + SH];
+                ts.ul[k][f] = C::F32 ? L.rl[f][i + SH] : 0.f;
             }
         }
         // quantities of V(s0) at the own points
@@ -758,15 +837,15 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t, const ProbDev& P, in
         if (first) {
             for (int idx = tid; idx < (t.npe + 1) * WL; idx += nth) {
                 const int b = idx / WL, w = idx - b * WL;
-                const int64_t x = wrapi(t.lo + L.pelo[b] - (int64_t)S * H + w, N);
+                const int r = L.pelo[b] + w;       // raw index of window position w
                 const int wp = b * WL + w;
                 Q q[F];
                 LR hv[F];
                 float lv[F];
 #pragma unroll
                 for (int f = 0; f < F; ++f) {
-                    hv[f] = st[f * N + x];
-                    lv[f] = use_lo ? stlo[f * N + x] : 0.f;
+                    hv[f] = L.rh[f][r];
+                    lv[f] = C::F32 ? L.rl[f][r] : 0.f;
                     L.wu[f][wp] = hv[f];
                     if constexpr (C::F32) {
                         L.wulo[f][wp] = lv[f];
@@ -784,27 +863,6 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t, const ProbDev& P, in
                 } else {
                     put_quant<C>(L.win[0], P, wp, q);
                 }
-            }
-        }
-        // delayed strips (and level n in per-stage mode) from the ring
-        const int nrec = S * H * F;
-        const int per = J * nrec;
-        for (int idx = tid; idx < 2 * t.npe * per; idx += nth) {
-            const int side_idx = idx / per, r = idx - side_idx * per;
-            const int l = r / nrec, rr = r - l * nrec;
-            const int s = rr / (H * F), h = (rr / F) % H, f = rr % F;
-            const int ke = L.keff[side_idx];
-            if (ke == 0 && (first || l > 0)) continue;   // from the window / weight 0
-            const int k = side_idx >> 1, side = side_idx & 1;
-            const int64_t m = n - ke - l;
-            const int so = side_idx * L.SOREC + ((l * S + s) * H + h) * F + f;
-            const unsigned char* rec = record_ptr<C>(P, m, t.pe0 + k, side);
-            if constexpr (C::F32) {
-                const float* rf = (const float*)rec;
-                L.SO[so] = rf[ring_lo_off<C>(s, h, f)];
-                if (s == 0) L.SOhi[((side_idx * L.jmax + l) * H + h) * F + f] = rf[h * F + f];
-            } else {
-                L.SO[so] = ((const double*)rec)[((int64_t)s * H + h) * F + f];
             }
         }
     });
