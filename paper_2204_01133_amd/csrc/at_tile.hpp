@@ -99,6 +99,55 @@ struct Tile {
 
 enum KFlags { KF_STAGE_IO = 1, KF_LOG = 2, KF_XCD = 4 };
 
+// Physics parameters of one problem, hoisted into registers at the start of a
+// tile (uniform across the workgroup: scalar registers on the GPU).
+struct PhysP {
+    int pde;
+    double c, alpha, r, gamma, q, ea, b, mu, kappa, rhoD, eps, inv_dx, inv_dx2, dt;
+};
+
+#if defined(__HIP_DEVICE_COMPILE__)
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ double uni(double v) {
+    union { double d; int i[2]; } u;
+    u.d = v;
+    u.i[0] = __builtin_amdgcn_readfirstlane(u.i[0]);
+    u.i[1] = __builtin_amdgcn_readfirstlane(u.i[1]);
+    return u.d;
+}
+__device__ __forceinline__ int64_t uni(int64_t v) {
+    union { int64_t l; int i[2]; } u;
+    u.l = v;
+    u.i[0] = __builtin_amdgcn_readfirstlane(u.i[0]);
+    u.i[1] = __builtin_amdgcn_readfirstlane(u.i[1]);
+    return u.l;
+}
+#else
+inline int uni(int v) { return v; }
+inline double uni(double v) { return v; }
+inline int64_t uni(int64_t v) { return v; }
+#endif
+
+// Butcher tableaus (eq. rk1) fixed by the stage count of the supported schemes:
+// S = 1 forward Euler, 2 Heun (eq. rk2), 3 SSP-RK3, 4 classical RK4.
+template <int S> struct RKTab;
+template <> struct RKTab<1> {
+    AT_HD static constexpr double a(int, int) { return 0.0; }
+    AT_HD static constexpr double b(int) { return 1.0; }
+};
+template <> struct RKTab<2> {
+    AT_HD static constexpr double a(int s, int i) { return (s == 1 && i == 0) ? 1.0 : 0.0; }
+    AT_HD static constexpr double b(int) { return 0.5; }
+};
+template <> struct RKTab<3> {
+    AT_HD static constexpr double a(int s, int i) { return s == 1 ? (i == 0 ? 1.0 : 0.0) : (s == 2 && i < 2 ? 0.25 : 0.0); }
+    AT_HD static constexpr double b(int s) { return s == 2 ? 2.0 / 3.0 : 1.0 / 6.0; }
+};
+template <> struct RKTab<4> {
+    AT_HD static constexpr double a(int s, int i) { return (s >= 1 && i == s - 1) ? (s == 3 ? 1.0 : 0.5) : 0.0; }
+    AT_HD static constexpr double b(int s) { return (s == 1 || s == 2) ? 1.0 / 3.0 : 1.0 / 6.0; }
+};
+
 struct KArgs {
     const Tile* tiles;
     const ProbDev* probs;
@@ -254,7 +303,7 @@ template <class R>
 AT_HD AT_FI R sq(R x) { return x * x; }
 
 // one-step chemistry, R = 1: T = (gamma-1)(E/rho - u^2/2 - q Y)
-AT_HD AT_FI void reactive_prims(const ProbDev& P, const double* q, double& rho, double& u, double& T,
+AT_HD AT_FI void reactive_prims(const PhysP& P, const double* q, double& rho, double& u, double& T,
                                 double& Y) {
     rho = q[0];
     u = q[1] / q[0];
@@ -263,7 +312,7 @@ AT_HD AT_FI void reactive_prims(const ProbDev& P, const double* q, double& rho, 
     T = (P.gamma - 1.0) * (E - 0.5 * u * u - P.q * Y);
 }
 
-AT_HD AT_FI double arrhenius(const ProbDev& P, const double* q) {
+AT_HD AT_FI double arrhenius(const PhysP& P, const double* q) {
     double rho, u, T, Y;
     reactive_prims(P, q, rho, u, T, Y);
     return -P.b * rho * Y * exp(-P.ea / T);
@@ -389,7 +438,7 @@ AT_HD AT_FI int64_t wrapi(int64_t x, int64_t n) {
 // ---------------------------------------------------------------------------
 // q: full state at the point (qreal).  For HILO the caller writes hi/lo itself.
 template <class C>
-AT_HD AT_FI void put_quant(const QV<C>& L, const ProbDev& P, int64_t e, const typename C::qreal* q) {
+AT_HD AT_FI void put_quant(const QV<C>& L, const PhysP& P, int64_t e, const typename C::qreal* q) {
     using Q = typename C::qreal;
     using LR = typename C::lreal;
     if constexpr (C::KIND == K_ADR) {
@@ -440,7 +489,7 @@ AT_HD AT_FI void put_quant(const QV<C>& L, const ProbDev& P, int64_t e, const ty
 
 // quantity values (qreal) of a state, without writing LDS: used by the halo fill
 template <class C>
-AT_HD AT_FI void quant_values(const ProbDev& P, const typename C::qreal* q, typename C::qreal* g,
+AT_HD AT_FI void quant_values(const PhysP& P, const typename C::qreal* q, typename C::qreal* g,
                               typename C::qreal& lam) {
     using Q = typename C::qreal;
     if constexpr (C::KIND == K_ADR) {
@@ -497,7 +546,7 @@ AT_HD AT_FI typename C::lreal d2(const View<typename C::lreal>& g, int64_t e) {
 
 // WENO interface flux between e and e+1 (local Lax-Friedrichs splitting)
 template <class C>
-AT_HD AT_FI void iface_flux(const QV<C>& L, const ProbDev& P, int64_t e) {
+AT_HD AT_FI void iface_flux(const QV<C>& L, const PhysP& P, int64_t e) {
     using LR = typename C::lreal;
     const LR a0 = L.lam[e], a1 = L.lam[e + 1];
     const LR al = a0 > a1 ? a0 : a1;
@@ -518,7 +567,7 @@ AT_HD AT_FI void iface_flux(const QV<C>& L, const ProbDev& P, int64_t e) {
 
 // K at ext position e; q = the point's own state (qreal) for sources / primitives
 template <class C>
-AT_HD AT_FI void rhs_at(const QV<C>& L, const ProbDev& P, int64_t e, const typename C::qreal* q,
+AT_HD AT_FI void rhs_at(const QV<C>& L, const PhysP& P, int64_t e, const typename C::qreal* q,
                         typename C::lreal* K) {
     using LR = typename C::lreal;
     if constexpr (C::KIND == K_ADR) {
@@ -604,11 +653,27 @@ template <class C>
 AT_HD AT_FI int64_t ring_lo_off(int s, int h, int f) { return (int64_t)C::H * C::F + ((int64_t)s * C::H + h) * C::F + f; }
 
 template <class C, class RT>
-AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t, const ProbDev& P, int64_t n,
+AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const ProbDev& P, int64_t n_in,
                      unsigned char* lds_base) {
     using LR = typename C::lreal;
     using Q = typename C::qreal;
     constexpr int F = C::F, H = C::H, S = C::S, PPT = C::PPT, WL = C::WL, NQ = C::NQ;
+
+    // tile and problem scalars, once per tile, uniform (scalar registers on the GPU)
+    Tile t;
+    t.prob = uni(t_in.prob);
+    t.pe0 = uni(t_in.pe0);
+    t.npe = uni(t_in.npe);
+    t.npts = uni(t_in.npts);
+    t.lo = uni(t_in.lo);
+    const int64_t n = uni(n_in);
+    PhysP PP;
+    PP.pde = uni(P.pde);
+    PP.c = uni(P.c); PP.alpha = uni(P.alpha); PP.r = uni(P.r); PP.gamma = uni(P.gamma);
+    PP.q = uni(P.q); PP.ea = uni(P.ea); PP.b = uni(P.b); PP.mu = uni(P.mu);
+    PP.kappa = uni(P.kappa); PP.rhoD = uni(P.rhoD); PP.eps = uni(P.eps);
+    PP.inv_dx = uni(P.inv_dx); PP.inv_dx2 = uni(P.inv_dx2); PP.dt = uni(P.dt);
+    using TB = RKTab<S>;
 
     // LDS layout sized by this tile (the launch allocates the largest over its tiles)
     Layout<C> Lo;
@@ -616,6 +681,7 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t, const ProbDev& P, in
     AT_CHECK(Lo.total <= a.lds_bytes, "tile LDS", Lo.total, a.lds_bytes);
     Lds<C> L;
     L.init(lds_base, Lo, t.npe, a.jmax);
+
 
     const int nth = rt.nthreads();
     const int s0 = a.s_begin, s1 = a.s_end;
@@ -625,9 +691,9 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t, const ProbDev& P, in
     const View<LR> st = st_view<C>(P, cur);
     const View<float> stlo = lo_view(P, cur, C::F32);
     const bool use_lo = C::F32 && P.keep_lo;
-    const int64_t N = P.n;
-    const int J = P.J;
-    const LR dt = LR(P.dt);
+    const int64_t N = uni(P.n);
+    const int J = uni(P.J);
+    const LR dt = LR(PP.dt);
     AT_CHECK(t.npts <= a.npts_max && t.npe <= a.npe_max, "tile size", t.npts, a.npts_max);
     AT_CHECK(J <= a.jmax && J <= JM, "jmax", J, a.jmax);
     AT_CHECK(t.npts <= nth * PPT, "points per thread", t.npts, nth * PPT);
@@ -781,9 +847,10 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t, const ProbDev& P, in
             if constexpr (C::F32) return (Q)ts.uh[k][f] + (Q)ts.ul[k][f];
             else return (Q)ts.uh[k][f];
         } else {
-            LR acc = LR(P.a[s][0]) * ts.K[0][k][f];
+            LR acc = LR(TB::a(s, 0)) * ts.K[0][k][f];
 #pragma unroll
-            for (int i = 1; i < s; ++i) acc += LR(P.a[s][i]) * ts.K[i][k][f];
+            for (int i = 1; i < s; ++i)
+                if (TB::a(s, i) != 0.0) acc += LR(TB::a(s, i)) * ts.K[i][k][f];
             if constexpr (C::F32) {
                 const float lo = ts.ul[k][f] + float(dt) * acc;
                 vlo = lo;
@@ -804,7 +871,7 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t, const ProbDev& P, in
             L.main.g[0][e] = ts.uh[k][0];
             L.main.glo[e] = vlo[0];
         } else {
-            put_quant<C>(L.main, P, e, q);
+            put_quant<C>(L.main, PP, e, q);
         }
     };
 
@@ -861,7 +928,7 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t, const ProbDev& P, in
                     L.win[0].g[0][wp] = hv[0];
                     L.win[0].glo[wp] = lv[0];
                 } else {
-                    put_quant<C>(L.win[0], P, wp, q);
+                    put_quant<C>(L.win[0], PP, wp, q);
                 }
             }
         }
@@ -932,7 +999,7 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t, const ProbDev& P, in
                                 if constexpr (C::F32) q[f] = (Q)L.SOhi[((sohb + l) * H + h) * F + f] + (Q)v;
                                 else q[f] = (Q)v;
                             }
-                            quant_values<C>(P, q, gl, laml);
+                            quant_values<C>(PP, q, gl, laml);
                             if (l == 0) {
                                 lam0 = laml;
 #pragma unroll
@@ -965,7 +1032,7 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t, const ProbDev& P, in
                     for (int k = 0; k < PPT; ++k) {
                         const int e = ts.e[k];
                         if (e < 0) continue;
-                        iface_flux<C>(L.main, P, e);              // right interface of the point
+                        iface_flux<C>(L.main, PP, e);              // right interface of the point
                         // left interface of the PE's first point: its left neighbour is a halo slot
                         const int i = tid + k * nth;
                         int lo = 0, hi = t.npe;
@@ -973,7 +1040,7 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t, const ProbDev& P, in
                             const int mid = (lo + hi) >> 1;
                             if (L.pelo[mid] <= i) lo = mid; else hi = mid;
                         }
-                        if (L.pelo[lo] == i) iface_flux<C>(L.main, P, e - 1);
+                        if (L.pelo[lo] == i) iface_flux<C>(L.main, PP, e - 1);
                     }
                 }
                 if (win_active) {
@@ -981,7 +1048,7 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t, const ProbDev& P, in
                     const int ni = rhi - rlo + 1;                 // interfaces rlo-1 .. rhi-1
                     for (int idx = tid; idx < (t.npe + 1) * ni; idx += nth) {
                         const int b = idx / ni, j = rlo - 1 + (idx - b * ni);
-                        iface_flux<C>(Wc, P, b * WL + j);
+                        iface_flux<C>(Wc, PP, b * WL + j);
                     }
                 }
             });
@@ -1000,7 +1067,7 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t, const ProbDev& P, in
 #pragma unroll
                     for (int f = 0; f < F; ++f) q[f] = own_state(ts, k, f, sc, vlo);
                     LR K[F];
-                    rhs_at<C>(L.main, P, e, q, K);
+                    rhs_at<C>(L.main, PP, e, q, K);
 #pragma unroll
                     for (int f = 0; f < F; ++f) ts.K[s][k][f] = K[f];
                 }
@@ -1018,16 +1085,17 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t, const ProbDev& P, in
                         else q[f] = (Q)L.wq[s & 1][f][wp];
                     }
                     LR K[F];
-                    rhs_at<C>(Wc, P, wp, q, K);
+                    rhs_at<C>(Wc, PP, wp, q, K);
                     Q qn[F];
                     LR hv[F];
                     float lvn[F];
 #pragma unroll
                     for (int f = 0; f < F; ++f) {
                         L.wR[s][f][wp] = K[f];
-                        LR acc = LR(P.a[s + 1][0]) * L.wR[0][f][wp];
+                        LR acc = LR(TB::a(s + 1, 0)) * L.wR[0][f][wp];
 #pragma unroll
-                        for (int i = 1; i <= s; ++i) acc += LR(P.a[s + 1][i]) * L.wR[i][f][wp];
+                        for (int i = 1; i <= s; ++i)
+                            if (TB::a(s + 1, i) != 0.0) acc += LR(TB::a(s + 1, i)) * L.wR[i][f][wp];
                         hv[f] = L.wu[f][wp];
                         if constexpr (C::F32) {
                             const float lo = L.wulo[f][wp] + float(dt) * acc;
@@ -1047,7 +1115,7 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t, const ProbDev& P, in
                         Wn.g[0][wp] = hv[0];
                         Wn.glo[wp] = lvn[0];
                     } else {
-                        put_quant<C>(Wn, P, wp, qn);
+                        put_quant<C>(Wn, PP, wp, qn);
                     }
                 }
             }
@@ -1075,9 +1143,9 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t, const ProbDev& P, in
             const View<float> dlo = lo_view(P, nxt, C::F32);
 #pragma unroll
             for (int f = 0; f < F; ++f) {
-                LR acc = LR(P.bw[0]) * ts.K[0][k][f];
+                LR acc = LR(TB::b(0)) * ts.K[0][k][f];
 #pragma unroll
-                for (int s = 1; s < S; ++s) acc += LR(P.bw[s]) * ts.K[s][k][f];
+                for (int s = 1; s < S; ++s) acc += LR(TB::b(s)) * ts.K[s][k][f];
                 if constexpr (C::F32) {
                     // compensated update: (hi, lo) + dt*acc, TwoSum of hi and (lo + dt*acc)
                     const float hi = ts.uh[k][f];
