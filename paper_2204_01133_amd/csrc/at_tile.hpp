@@ -104,6 +104,7 @@ enum KFlags { KF_STAGE_IO = 1, KF_LOG = 2, KF_XCD = 4 };
 struct PhysP {
     int pde;
     double c, alpha, r, gamma, q, ea, b, mu, kappa, rhoD, eps, inv_dx, inv_dx2, dt;
+    float cf, alphaf, rf, inv_dxf, inv_dx2f;     // FP32 copies for the FP32 forms
 };
 
 #if defined(__HIP_DEVICE_COMPILE__)
@@ -182,6 +183,8 @@ struct Cfg {
 
 AT_HD AT_FI int64_t align16(int64_t b) { return (b + 15) & ~int64_t(15); }
 
+constexpr int JMAXW = 8;   // row length of the LDS table of extrapolation weights
+
 // LDS layout of a launch (same function on host and device).
 //   main region (per PE of the tile: H halo slots, own points, H halo slots)
 //   window region (one window of 2*S*H positions per PE boundary), with the
@@ -192,7 +195,7 @@ struct Layout {
     int64_t EXM, EXW, NW, SOREC;
     int64_t EXR;   // raw staging range [lo - S*H, lo + npts + S*H)
     int64_t o_g, o_glo, o_lam, o_flux, o_gw, o_gwlo, o_lamw, o_fluxw, o_wu, o_wulo, o_wq, o_wR,
-        o_SO, o_SOhi, o_pelo, o_keff, o_rh, o_rl, total;
+        o_SO, o_SOhi, o_pelo, o_keff, o_wt, o_rh, o_rl, total;
     AT_HD void init(int npts_max, int npe_max, int jmax) {
         using L = typename C::lreal;
         const int64_t sl = (int64_t)sizeof(L);
@@ -220,6 +223,7 @@ struct Layout {
         o_SOhi = o;  o += C::F32 ? align16(2 * (int64_t)npe_max * jmax * C::H * C::F * 4) : 0;
         o_pelo = o;  o += align16((npe_max + 1) * 4);
         o_keff = o;  o += align16(2 * (int64_t)npe_max * 4);
+        o_wt = o;    o += align16(16 * JMAXW * 8);      // extrapolation weights [k][l]
         o_rh = o;    o += align16(C::F * EXR * sl);
         o_rl = o;    o += C::F32 ? align16(C::F * EXR * 4) : 0;
         total = o;
@@ -370,6 +374,7 @@ struct Lds {
     View<L> SO;
     View<float> SOhi;
     View<int> pelo, keff;
+    View<double> wt;           // extrapolation weights w_l(k) at [k * JMAXW + l]
     View<L> rh[C::F];          // raw u^n (FP64 value / FP32 hi) on [lo - S*H, lo + npts + S*H)
     View<float> rl[C::F];      // raw FP32 lo
     int EXM, EXW, SOREC, jmax;
@@ -412,6 +417,7 @@ struct Lds {
         SOhi = View<float>{(float*)(base + Lo.o_SOhi), C::F32 ? 2 * (int64_t)npe_max * jm * C::H * C::F : 0};
         pelo = View<int>{(int*)(base + Lo.o_pelo), npe_max + 1};
         keff = View<int>{(int*)(base + Lo.o_keff), 2 * (int64_t)npe_max};
+        wt = View<double>{(double*)(base + Lo.o_wt), 16 * JMAXW};
         for (int f = 0; f < C::F; ++f) {
             rh[f] = View<L>{(L*)(base + Lo.o_rh) + f * Lo.EXR, Lo.EXR};
             rl[f] = View<float>{(float*)(base + Lo.o_rl) + f * Lo.EXR, C::F32 ? Lo.EXR : 0};
@@ -580,10 +586,10 @@ AT_HD AT_FI void rhs_at(const QV<C>& L, const PhysP& P, int64_t e, const typenam
                 s1 += float(FD<C::H>::c1(o)) * ((hp - hm) + (lp - lm));
                 s2 += float(FD<C::H>::c2(o)) * (((hp - hc) + (lp - lc)) + ((hm - hc) + (lm - lc)));
             }
-            float k = -float(P.c) * (s1 * float(P.inv_dx)) + float(P.alpha) * (s2 * float(P.inv_dx2));
+            float k = -P.cf * (s1 * P.inv_dxf) + P.alphaf * (s2 * P.inv_dx2f);
             if (P.pde == PDE_ADR_LOGISTIC) {
                 const float u = hc + lc;
-                k += float(P.r) * u * (1.f - u);
+                k += P.rf * u * (1.f - u);
             }
             K[0] = k;
         } else {
@@ -673,6 +679,13 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const ProbDev& P,
     PP.q = uni(P.q); PP.ea = uni(P.ea); PP.b = uni(P.b); PP.mu = uni(P.mu);
     PP.kappa = uni(P.kappa); PP.rhoD = uni(P.rhoD); PP.eps = uni(P.eps);
     PP.inv_dx = uni(P.inv_dx); PP.inv_dx2 = uni(P.inv_dx2); PP.dt = uni(P.dt);
+    PP.cf = (float)PP.c; PP.alphaf = (float)PP.alpha; PP.rf = (float)PP.r;
+    PP.inv_dxf = (float)PP.inv_dx; PP.inv_dx2f = (float)PP.inv_dx2;
+    // memory of the problem (uniform)
+    const int64_t Pp = uni((int64_t)P.p);
+    const int Dring = uni(P.D);
+    const int64_t recb = uni(P.rec_bytes);
+    unsigned char* const ring = (unsigned char*)uni((int64_t)(uintptr_t)P.ring);
     using TB = RKTab<S>;
 
     // LDS layout sized by this tile (the launch allocates the largest over its tiles)
@@ -698,9 +711,17 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const ProbDev& P,
     AT_CHECK(J <= a.jmax && J <= JM, "jmax", J, a.jmax);
     AT_CHECK(t.npts <= nth * PPT, "points per thread", t.npts, nth * PPT);
 
+    // strip ring record of PE (t.pe0 + k), side, at level m
+    auto rec_at = [&](int64_t m, int k, int side) -> unsigned char* {
+        int64_t slot = m % Dring;
+        if (slot < 0) slot += Dring;
+        const int64_t idx = (slot * Pp + t.pe0 + k) * 2 + side;
+        AT_CHECK(idx >= 0 && idx < (int64_t)Dring * Pp * 2, "ring record", idx, (int64_t)Dring * Pp * 2);
+        return ring + idx * recb;
+    };
     // ring record of PE (t.pe0 + k), side, level n: stage s at halo point h
     auto rec_store = [&](int k, int side, int s, int h, int f, LR v, float hi) {
-        unsigned char* rec = record_ptr<C>(P, n, t.pe0 + k, side);
+        unsigned char* rec = rec_at(n, k, side);
         if constexpr (C::F32) {
             float* rf = (float*)rec;
             rf[ring_lo_off<C>(s, h, f)] = v;
@@ -781,8 +802,14 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const ProbDev& P,
             }
         }
         for (int k = tid; k <= t.npe; k += nth) {
-            const int64_t lo = ((int64_t)(t.pe0 + k) * N) / P.p;
+            const int64_t lo = ((int64_t)(t.pe0 + k) * N) / Pp;
             L.pelo[k] = (int)(lo - t.lo);
+        }
+        if (tid < 16) {   // Lagrange weights for delay k = tid (J levels; k = 0 uses one level)
+            double w[JM];
+            lagrange_weights(tid == 0 ? 1 : J, tid, w);
+#pragma unroll
+            for (int l = 0; l < JM; ++l) L.wt[tid * JMAXW + l] = w[l];
         }
         constexpr int nrec = S * H * F;
         for (int side_idx = tid; side_idx < 2 * t.npe; side_idx += nth) {
@@ -801,7 +828,7 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const ProbDev& P,
 #pragma unroll
             for (int l = 0; l < JM; ++l) {
                 if (l >= jeff) continue;
-                const unsigned char* rec = record_ptr<C>(P, n - ke - l, t.pe0 + k, side);
+                const unsigned char* rec = rec_at(n - ke - l, k, side);
                 const int sob = side_idx * L.SOREC + l * nrec;
                 LR v[nrec];
                 float vh[C::F32 ? H * F : 1];
@@ -970,7 +997,8 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const ProbDev& P,
                     }
                     const int jeff = ke == 0 ? 1 : J;
                     double w[JM];
-                    lagrange_weights(jeff, ke, w);
+#pragma unroll
+                    for (int l = 0; l < JM; ++l) w[l] = L.wt[ke * JMAXW + l];
                     const int sob = side_idx * L.SOREC;
                     const int sohb = side_idx * L.jmax;
                     if constexpr (C::HILO) {
