@@ -261,6 +261,31 @@ AT_HD AT_FI int draw_delay(const ProbDev& P, int64_t step, int64_t idx, int side
 // Lagrange weights from levels -k..-k-J+1 to 0: w_l = prod_{m!=l} (k+m)/(m-l), exact
 // integers; fixed-size loops (JM >= J) so that w stays in registers.
 constexpr int JM = 6;
+
+// The same weights tabulated at compile time: WTAB.w[J][k][l], J = 1..JM, k = 0..15.
+struct WeightTable {
+    double w[JM + 1][16][8];
+};
+constexpr WeightTable make_weight_table() {
+    WeightTable t{};
+    for (int J = 1; J <= JM; ++J)
+        for (int k = 0; k < 16; ++k)
+            for (int l = 0; l < J; ++l) {
+                long long num = 1, den = 1;
+                for (int m = 0; m < J; ++m) {
+                    if (m == l) continue;
+                    num *= (long long)(k + m);
+                    den *= (long long)(m - l);
+                }
+                t.w[J][k][l] = (double)(num / den);
+            }
+    return t;
+}
+#if defined(__HIPCC__)
+__constant__ constexpr WeightTable WTAB = make_weight_table();
+#else
+constexpr WeightTable WTAB = make_weight_table();
+#endif
 AT_HD AT_FI void lagrange_weights(int J, int k, double (&w)[JM]) {
 #pragma unroll
     for (int l = 0; l < JM; ++l) {
@@ -424,6 +449,13 @@ struct Lds {
         }
     }
 };
+
+// Small per-PE / per-side work lists: item j goes to thread (j % 4) * 64 + j / 4 so
+// that consecutive items land in different wavefronts of a 256-thread group
+// (returns the first item of thread tid; step by nth as usual).
+AT_HD AT_FI int spread(int tid, int nth) {
+    return nth == 256 ? ((tid & 63) << 2) | (tid >> 6) : tid;
+}
 
 // compile-time loop: f(std::integral_constant<int, I>) for I in [B, E)
 template <int B, int E, class Fn>
@@ -801,18 +833,16 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const ProbDev& P,
                 }
             }
         }
-        for (int k = tid; k <= t.npe; k += nth) {
+        for (int k = spread(tid, nth); k <= t.npe; k += nth) {
             const int64_t lo = ((int64_t)(t.pe0 + k) * N) / Pp;
             L.pelo[k] = (int)(lo - t.lo);
         }
-        if (tid < 16) {   // Lagrange weights for delay k = tid (J levels; k = 0 uses one level)
-            double w[JM];
-            lagrange_weights(tid == 0 ? 1 : J, tid, w);
-#pragma unroll
-            for (int l = 0; l < JM; ++l) L.wt[tid * JMAXW + l] = w[l];
+        if (tid < 16 * JMAXW) {   // weights for delay k (J levels; k = 0 uses one level)
+            const int k = tid / JMAXW, l = tid % JMAXW;
+            L.wt[tid] = l < JM ? WTAB.w[k == 0 ? 1 : J][k][l] : 0.0;
         }
         constexpr int nrec = S * H * F;
-        for (int side_idx = tid; side_idx < 2 * t.npe; side_idx += nth) {
+        for (int side_idx = spread(tid, nth); side_idx < 2 * t.npe; side_idx += nth) {
             const int k = side_idx >> 1, side = side_idx & 1;
             int kd;
             const int ke = delays_of(k, side, kd);
@@ -866,6 +896,19 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const ProbDev& P,
     });
     rt.sync();
 
+    // tile-local PE of own point i: the PE owning global x is floor(((x+1) P - 1) / N);
+    // estimated in double as floor((x+1) P/N - 1e-9) (off by at most one for huge N)
+    // and corrected against the tile's PE offsets
+    const double PoverN = (double)Pp / (double)N;
+    auto pe_local = [&](int i) -> int {
+        const int64_t x = t.lo + i;
+        int pl = (int)((int64_t)((double)(x + 1) * PoverN - 1e-9) - t.pe0);
+        pl = pl < 0 ? 0 : (pl >= t.npe ? t.npe - 1 : pl);
+        if (L.pelo[pl] > i) --pl;
+        else if (L.pelo[pl + 1] <= i) ++pl;
+        return pl;
+    };
+
     // own stage state V(s) = u^n + dt sum_{i<s} a_si K_i of slot k, field f
     auto own_state = [&](const TS<C>& ts, int k, int f, auto sc, float& vlo) -> Q {
         constexpr int s = decltype(sc)::value;
@@ -909,11 +952,7 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const ProbDev& P,
             const int i = tid + k * nth;
             ts.e[k] = -1;
             if (i >= t.npts) continue;
-            int lo = 0, hi = t.npe;   // pelo[lo] <= i < pelo[hi]
-            while (hi - lo > 1) {
-                const int mid = (lo + hi) >> 1;
-                if (L.pelo[mid] <= i) lo = mid; else hi = mid;
-            }
+            const int lo = pe_local(i);
             ts.e[k] = i + 2 * H * lo + H;
 #pragma unroll
             for (int f = 0; f < F; ++f) {
@@ -929,7 +968,7 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const ProbDev& P,
                 if (ts.e[k] >= 0) own_quant(ts, k, sc);
         });
         if (first) {
-            for (int idx = tid; idx < (t.npe + 1) * WL; idx += nth) {
+            for (int idx = spread(tid, nth); idx < (t.npe + 1) * WL; idx += nth) {
                 const int b = idx / WL, w = idx - b * WL;
                 const int r = L.pelo[b] + w;       // raw index of window position w
                 const int wp = b * WL + w;
@@ -979,7 +1018,7 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const ProbDev& P,
                     for (int k = 0; k < PPT; ++k)
                         if (ts.e[k] >= 0) own_quant(ts, k, sc);
                 }
-                for (int idx = tid; idx < 2 * t.npe * H; idx += nth) {
+                for (int idx = spread(tid, nth); idx < 2 * t.npe * H; idx += nth) {
                     const int side_idx = idx / H, h = idx - side_idx * H;
                     const int k = side_idx >> 1, side = side_idx & 1;
                     const int ke = L.keff[side_idx];
@@ -1063,18 +1102,13 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const ProbDev& P,
                         iface_flux<C>(L.main, PP, e);              // right interface of the point
                         // left interface of the PE's first point: its left neighbour is a halo slot
                         const int i = tid + k * nth;
-                        int lo = 0, hi = t.npe;
-                        while (hi - lo > 1) {
-                            const int mid = (lo + hi) >> 1;
-                            if (L.pelo[mid] <= i) lo = mid; else hi = mid;
-                        }
-                        if (L.pelo[lo] == i) iface_flux<C>(L.main, PP, e - 1);
+                        if (L.pelo[pe_local(i)] == i) iface_flux<C>(L.main, PP, e - 1);
                     }
                 }
                 if (win_active) {
                     const int rlo = (s + 1) * H, rhi = WL - (s + 1) * H;
                     const int ni = rhi - rlo + 1;                 // interfaces rlo-1 .. rhi-1
-                    for (int idx = tid; idx < (t.npe + 1) * ni; idx += nth) {
+                    for (int idx = spread(tid, nth); idx < (t.npe + 1) * ni; idx += nth) {
                         const int b = idx / ni, j = rlo - 1 + (idx - b * ni);
                         iface_flux<C>(Wc, PP, b * WL + j);
                     }
@@ -1103,7 +1137,7 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const ProbDev& P,
             if (win_active) {
                 const int rlo = (s + 1) * H, rhi = WL - (s + 1) * H;
                 const int nr = rhi - rlo;
-                for (int idx = tid; idx < (t.npe + 1) * nr; idx += nth) {
+                for (int idx = spread(tid, nth); idx < (t.npe + 1) * nr; idx += nth) {
                     const int b = idx / nr, w = rlo + (idx - b * nr);
                     const int wp = b * WL + w;
                     Q q[F];
