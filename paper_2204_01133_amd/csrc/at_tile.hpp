@@ -246,11 +246,17 @@ AT_HD AT_FI uint64_t mix64(uint64_t z) {
     return z ^ (z >> 31);
 }
 
-AT_HD AT_FI int draw_delay(const ProbDev& P, int64_t step, int64_t idx, int side) {
-    const uint64_t g = 0x9e3779b97f4a7c15ULL;
-    uint64_t z = mix64(P.seed + g * (uint64_t)(P.pid + 1));
-    z = mix64(z + g * (uint64_t)(step + 1));
-    z = mix64(z + g * (uint64_t)(2 * idx + side + 1));
+constexpr uint64_t GOLDEN = 0x9e3779b97f4a7c15ULL;
+
+// the (seed, problem, step) part of the counter chain: the same for every PE of a step
+AT_HD AT_FI uint64_t delay_prefix(const ProbDev& P, int64_t step) {
+    const uint64_t z = mix64(P.seed + GOLDEN * (uint64_t)(P.pid + 1));
+    return mix64(z + GOLDEN * (uint64_t)(step + 1));
+}
+
+// delay of counter (idx, side) given the step's prefix
+AT_HD AT_FI int draw_delay(const ProbDev& P, uint64_t prefix, int64_t idx, int side) {
+    const uint64_t z = mix64(prefix + GOLDEN * (uint64_t)(2 * idx + side + 1));
     const uint64_t top = z >> 32;
     if (P.n_cdf == 0) return (int)((top * (uint64_t)(P.kmax + 1)) >> 32);
     int k = 0;
@@ -666,13 +672,6 @@ AT_HD AT_FI View<float> lo_view(const ProbDev& P, int which, bool f32) {
     return View<float>{(float*)P.st_lo[which], f32 ? (int64_t)P.F * P.n : 0};
 }
 
-template <class C>
-AT_HD AT_FI unsigned char* record_ptr(const ProbDev& P, int64_t level, int64_t pe, int side) {
-    const int64_t slot = wrapi(level, P.D);
-    const int64_t idx = (slot * P.p + pe) * 2 + side;
-    AT_CHECK(idx >= 0 && idx < (int64_t)P.D * P.p * 2, "ring record", idx, (int64_t)P.D * P.p * 2);
-    return (unsigned char*)P.ring + idx * P.rec_bytes;
-}
 
 // ---------------------------------------------------------------------------
 // the tile step
@@ -743,17 +742,25 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const ProbDev& P,
     AT_CHECK(J <= a.jmax && J <= JM, "jmax", J, a.jmax);
     AT_CHECK(t.npts <= nth * PPT, "points per thread", t.npts, nth * PPT);
 
-    // strip ring record of PE (t.pe0 + k), side, at level m
-    auto rec_at = [&](int64_t m, int k, int side) -> unsigned char* {
-        int64_t slot = m % Dring;
+    // strip ring: slot of level n (levels n - d, 0 <= d < D, are slot_n - d mod D),
+    // records of the tile's PEs at a slot are 2 * npe consecutive records
+    const int slot_n = uni((int)(n % Dring));
+    const int64_t slot_stride = Pp * 2 * recb;
+    unsigned char* const ring_tile = ring + (int64_t)t.pe0 * 2 * recb;
+    // record of PE (t.pe0 + k), side, at level n - d
+    auto rec_back = [&](int d, int k, int side) -> unsigned char* {
+        AT_CHECK(d >= 0 && d < Dring, "ring depth", d, Dring);
+        int slot = slot_n - d;
         if (slot < 0) slot += Dring;
-        const int64_t idx = (slot * Pp + t.pe0 + k) * 2 + side;
+        const int64_t idx = ((int64_t)slot * Pp + t.pe0 + k) * 2 + side;
         AT_CHECK(idx >= 0 && idx < (int64_t)Dring * Pp * 2, "ring record", idx, (int64_t)Dring * Pp * 2);
-        return ring + idx * recb;
+        return ring_tile + (int64_t)slot * slot_stride + (int64_t)(2 * k + side) * recb;
     };
+    unsigned char* const ring_n = ring_tile + (int64_t)slot_n * slot_stride;
     // ring record of PE (t.pe0 + k), side, level n: stage s at halo point h
     auto rec_store = [&](int k, int side, int s, int h, int f, LR v, float hi) {
-        unsigned char* rec = rec_at(n, k, side);
+        AT_CHECK(k >= 0 && k < t.npe, "ring store", k, t.npe);
+        unsigned char* rec = ring_n + (int64_t)(2 * k + side) * recb;
         if constexpr (C::F32) {
             float* rf = (float*)rec;
             rf[ring_lo_off<C>(s, h, f)] = v;
@@ -774,6 +781,7 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const ProbDev& P,
     };
 
     // delay of PE (t.pe0 + k), side: drawn and effective (clamped to the held history)
+    const uint64_t dprefix = uni((int64_t)delay_prefix(P, n));
     auto delays_of = [&](int k, int side, int& kd) -> int {
         const int64_t pe = t.pe0 + k;
         if (P.ov && n >= P.ov_step0 && n < P.ov_step0 + P.ov_n) {
@@ -781,11 +789,11 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const ProbDev& P,
             AT_CHECK(oi >= 0 && oi < P.ov_n * P.p * 2, "override", oi, P.ov_n * P.p * 2);
             kd = P.ov[oi];
         } else if (P.gran == G_PE) {
-            kd = draw_delay(P, n, pe, 0);
+            kd = draw_delay(P, dprefix, pe, 0);
         } else if (P.gran == G_PE_SIDE) {
-            kd = draw_delay(P, n, pe, side);
+            kd = draw_delay(P, dprefix, pe, side);
         } else {
-            kd = draw_delay(P, n, side == 0 ? pe : (pe + 1 == P.p ? 0 : pe + 1), 0);
+            kd = draw_delay(P, dprefix, side == 0 ? pe : (pe + 1 == P.p ? 0 : pe + 1), 0);
         }
         int ke;
         if (P.mode == M_AT) {
@@ -804,6 +812,7 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const ProbDev& P,
     //   raw u^n on [lo - S*H, lo + npts + S*H) (own points and boundary windows),
     //   PE offsets, delays, delayed strips of the ring, stage inputs (per-stage mode)
     constexpr int SH = S * H;
+    const double invP = 1.0 / (double)Pp;
     rt.each([&](int tid, TS<C>& ts) {
         const int nraw = t.npts + 2 * SH;
         AT_CHECK(nraw <= nth * (PPT + 1), "raw range", nraw, nth * (PPT + 1));
@@ -815,7 +824,8 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const ProbDev& P,
                 const int r = tid + k * nth;
                 if (r >= nraw) continue;
                 int64_t x = t.lo - SH + r;
-                if (x < 0 || x >= N) x = wrapi(x, N);
+                if (x < 0) x = N >= SH ? x + N : wrapi(x, N);
+                else if (x >= N) x = N >= SH ? x - N : wrapi(x, N);
 #pragma unroll
                 for (int f = 0; f < F; ++f) {
                     vh[k][f] = st[f * N + x];
@@ -834,7 +844,12 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const ProbDev& P,
             }
         }
         for (int k = spread(tid, nth); k <= t.npe; k += nth) {
-            const int64_t lo = ((int64_t)(t.pe0 + k) * N) / Pp;
+            // floor(p N / P) of PE p = pe0 + k: estimated in double, then corrected exactly
+            const int64_t num = (int64_t)(t.pe0 + k) * N;
+            int64_t lo = (int64_t)((double)num * invP);
+            if (lo * Pp > num) --lo;
+            else if ((lo + 1) * Pp <= num) ++lo;
+            AT_CHECK(lo * Pp <= num && (lo + 1) * Pp > num, "PE offset", lo, num);
             L.pelo[k] = (int)(lo - t.lo);
         }
         if (tid < 16 * JMAXW) {   // weights for delay k (J levels; k = 0 uses one level)
@@ -858,7 +873,7 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const ProbDev& P,
 #pragma unroll
             for (int l = 0; l < JM; ++l) {
                 if (l >= jeff) continue;
-                const unsigned char* rec = rec_at(n - ke - l, k, side);
+                const unsigned char* rec = rec_back(ke + l, k, side);
                 const int sob = side_idx * L.SOREC + l * nrec;
                 LR v[nrec];
                 float vh[C::F32 ? H * F : 1];
