@@ -456,11 +456,12 @@ struct Lds {
     }
 };
 
-// Small per-PE / per-side work lists: item j goes to thread (j % 4) * 64 + j / 4 so
-// that consecutive items land in different wavefronts of a 256-thread group
-// (returns the first item of thread tid; step by nth as usual).
-AT_HD AT_FI int spread(int tid, int nth) {
-    return nth == 256 ? ((tid & 63) << 2) | (tid >> 6) : tid;
+// First item of thread tid in a short work list (a few items per PE) whose items
+// are to fill wavefront r of a 256-thread group first, then r+1, ...: a list of
+// m items costs ceil(m / 64) wavefront passes instead of one pass in every
+// wavefront, and lists of different phases start in different wavefronts.
+AT_HD AT_FI int first_item(int tid, int nth, int r) {
+    return nth == 256 ? ((tid + 256 - 64 * (r & 3)) & 255) : tid;
 }
 
 // compile-time loop: f(std::integral_constant<int, I>) for I in [B, E)
@@ -843,7 +844,7 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const ProbDev& P,
                 }
             }
         }
-        for (int k = spread(tid, nth); k <= t.npe; k += nth) {
+        for (int k = first_item(tid, nth, 3); k <= t.npe; k += nth) {
             // floor(p N / P) of PE p = pe0 + k: estimated in double, then corrected exactly
             const int64_t num = (int64_t)(t.pe0 + k) * N;
             int64_t lo = (int64_t)((double)num * invP);
@@ -857,7 +858,7 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const ProbDev& P,
             L.wt[tid] = l < JM ? WTAB.w[k == 0 ? 1 : J][k][l] : 0.0;
         }
         constexpr int nrec = S * H * F;
-        for (int side_idx = spread(tid, nth); side_idx < 2 * t.npe; side_idx += nth) {
+        for (int side_idx = first_item(tid, nth, 1); side_idx < 2 * t.npe; side_idx += nth) {
             const int k = side_idx >> 1, side = side_idx & 1;
             int kd;
             const int ke = delays_of(k, side, kd);
@@ -983,7 +984,7 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const ProbDev& P,
                 if (ts.e[k] >= 0) own_quant(ts, k, sc);
         });
         if (first) {
-            for (int idx = spread(tid, nth); idx < (t.npe + 1) * WL; idx += nth) {
+            for (int idx = first_item(tid, nth, 0); idx < (t.npe + 1) * WL; idx += nth) {
                 const int b = idx / WL, w = idx - b * WL;
                 const int r = L.pelo[b] + w;       // raw index of window position w
                 const int wp = b * WL + w;
@@ -1033,7 +1034,7 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const ProbDev& P,
                     for (int k = 0; k < PPT; ++k)
                         if (ts.e[k] >= 0) own_quant(ts, k, sc);
                 }
-                for (int idx = spread(tid, nth); idx < 2 * t.npe * H; idx += nth) {
+                for (int idx = first_item(tid, nth, s + 2); idx < 2 * t.npe * H; idx += nth) {
                     const int side_idx = idx / H, h = idx - side_idx * H;
                     const int k = side_idx >> 1, side = side_idx & 1;
                     const int ke = L.keff[side_idx];
@@ -1123,7 +1124,7 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const ProbDev& P,
                 if (win_active) {
                     const int rlo = (s + 1) * H, rhi = WL - (s + 1) * H;
                     const int ni = rhi - rlo + 1;                 // interfaces rlo-1 .. rhi-1
-                    for (int idx = spread(tid, nth); idx < (t.npe + 1) * ni; idx += nth) {
+                    for (int idx = first_item(tid, nth, 2 * s + 1); idx < (t.npe + 1) * ni; idx += nth) {
                         const int b = idx / ni, j = rlo - 1 + (idx - b * ni);
                         iface_flux<C>(Wc, PP, b * WL + j);
                     }
@@ -1152,7 +1153,7 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const ProbDev& P,
             if (win_active) {
                 const int rlo = (s + 1) * H, rhi = WL - (s + 1) * H;
                 const int nr = rhi - rlo;
-                for (int idx = spread(tid, nth); idx < (t.npe + 1) * nr; idx += nth) {
+                for (int idx = first_item(tid, nth, 2 * s); idx < (t.npe + 1) * nr; idx += nth) {
                     const int b = idx / nr, w = rlo + (idx - b * nr);
                     const int wp = b * WL + w;
                     Q q[F];
