@@ -106,11 +106,15 @@ typedef struct at_problem_desc {
  *   log_steps       capacity, in steps, of the device delay log (0 = off).
  *   override_steps  capacity, in steps, of the delay-override buffer (0 = off).
  *   stage_api       1 = reserve the stage buffers that at_rk_stage needs.
+ *   lds_budget      bytes of LDS per tile the planner packs PEs up to (0 = default
+ *                   40 KiB, 4 workgroups per compute unit); a tile of one PE may
+ *                   exceed it (up to the 160 KiB of a compute unit).
  */
 typedef struct at_run_opts {
     int32_t tile_points, persistent, grid_per_cu, graph_steps;
     int32_t xcd_remap, log_steps, override_steps, stage_api;
-    int32_t reserved[8];
+    int32_t lds_budget;
+    int32_t reserved[7];
 } at_run_opts;
 
 typedef struct at_ctx at_ctx;

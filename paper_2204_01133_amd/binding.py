@@ -52,7 +52,7 @@ class AtRunOpts(ctypes.Structure):
         ("grid_per_cu", ctypes.c_int32), ("graph_steps", ctypes.c_int32),
         ("xcd_remap", ctypes.c_int32), ("log_steps", ctypes.c_int32),
         ("override_steps", ctypes.c_int32), ("stage_api", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 8),
+        ("lds_budget", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7),
     ]
 
 

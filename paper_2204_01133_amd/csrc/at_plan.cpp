@@ -140,7 +140,7 @@ int make_plan(const at_problem_desc* probs, int n_probs, const at_run_opts* opts
     std::memset(&plan.opts, 0, sizeof(plan.opts));
     if (opts) plan.opts = *opts;
     if (plan.opts.log_steps < 0 || plan.opts.override_steps < 0 || plan.opts.tile_points < 0 ||
-        plan.opts.graph_steps < 0 || plan.opts.grid_per_cu < 0) {
+        plan.opts.graph_steps < 0 || plan.opts.grid_per_cu < 0 || plan.opts.lds_budget < 0) {
         err = "negative option";
         return AT_EINVAL;
     }
@@ -172,7 +172,7 @@ int make_plan(const at_problem_desc* probs, int n_probs, const at_run_opts* opts
 
     // ---- tiles: whole PEs packed up to the tile target and the LDS budget; a PE
     //      larger than a small tile gets a tile of the large points-per-thread class ----
-    const int64_t lds_budget = 30 * 1024;     // ~5 workgroups per CU
+    const int64_t lds_budget = plan.opts.lds_budget > 0 ? plan.opts.lds_budget : 40 * 1024;
     const int64_t lds_hard = 160 * 1024;
     std::vector<std::vector<Tile>> small(n_probs), large(n_probs);
     for (int b = 0; b < n_probs; ++b) {

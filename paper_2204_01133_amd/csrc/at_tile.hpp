@@ -149,6 +149,16 @@ template <> struct RKTab<4> {
     AT_HD static constexpr double b(int s) { return (s == 1 || s == 2) ? 1.0 / 3.0 : 1.0 / 6.0; }
 };
 
+// Whether a window stage update needs a right-hand side older than the current
+// stage (a_{s+1,i} != 0 for some i < s); if not, the window stage RHS are not kept.
+template <int S>
+AT_HD constexpr bool rk_keeps_stage_rhs() {
+    for (int s = 1; s + 1 <= S - 1; ++s)
+        for (int i = 0; i < s; ++i)
+            if (RKTab<S>::a(s + 1, i) != 0.0) return true;
+    return false;
+}
+
 struct KArgs {
     const Tile* tiles;
     const ProbDev* probs;
@@ -206,10 +216,17 @@ struct Layout {
         EXR = npts_max + 2 * C::S * C::H;
         const int64_t SR = C::S > 1 ? C::S - 1 : 1;
         int64_t o = 0;
+        // the raw range is consumed before the main region is first written
+        // (a barrier apart), so the two share the front of the layout
+        o_rh = o;    o += align16(C::F * EXR * sl);
+        o_rl = o;    o += C::F32 ? align16(C::F * EXR * 4) : 0;
+        const int64_t raw_end = o;
+        o = 0;
         o_g = o;     o += align16(C::NQ * EXM * sl);
         o_glo = o;   o += C::HILO ? align16(EXM * 4) : 0;
         o_lam = o;   o += C::WENO ? align16(EXM * sl) : 0;
         o_flux = o;  o += C::WENO ? align16(C::F * EXM * sl) : 0;
+        if (o < raw_end) o = raw_end;
         // the scalar FD kind's window quantities are its window state (aliased below)
         o_gw = o;    o += C::KIND == K_ADR ? 0 : align16(2 * C::NQ * EXW * sl);
         o_gwlo = o;
@@ -218,14 +235,12 @@ struct Layout {
         o_wu = o;    o += align16(C::F * EXW * sl);
         o_wulo = o;  o += C::F32 ? align16(C::F * EXW * 4) : 0;
         o_wq = o;    o += align16(2 * C::F * EXW * sl);
-        o_wR = o;    o += align16(SR * C::F * EXW * sl);
+        o_wR = o;    o += rk_keeps_stage_rhs<C::S>() ? align16(SR * C::F * EXW * sl) : 0;
         o_SO = o;    o += align16(2 * (int64_t)npe_max * SOREC * sl);
         o_SOhi = o;  o += C::F32 ? align16(2 * (int64_t)npe_max * jmax * C::H * C::F * 4) : 0;
         o_pelo = o;  o += align16((npe_max + 1) * 4);
         o_keff = o;  o += align16(2 * (int64_t)npe_max * 4);
         o_wt = o;    o += align16(16 * JMAXW * 8);      // extrapolation weights [k][l]
-        o_rh = o;    o += align16(C::F * EXR * sl);
-        o_rl = o;    o += C::F32 ? align16(C::F * EXR * 4) : 0;
         total = o;
     }
 };
@@ -431,7 +446,8 @@ struct Lds {
             for (int par = 0; par < 2; ++par)
                 wq[par][f] = View<L>{(L*)(base + Lo.o_wq) + (par * C::F + f) * nw, nw};
             for (int r = 0; r < SR; ++r)
-                wR[r][f] = View<L>{(L*)(base + Lo.o_wR) + (r * C::F + f) * nw, nw};
+                wR[r][f] = View<L>{(L*)(base + Lo.o_wR) + (r * C::F + f) * nw,
+                                   rk_keeps_stage_rhs<C::S>() ? nw : 0};
         }
         if constexpr (C::KIND == K_ADR) {
             // window quantity g = stage state: FP64 value, or FP32 hi (= raw hi) with lo
@@ -976,13 +992,6 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const ProbDev& P,
                 ts.ul[k][f] = C::F32 ? L.rl[f][i + SH] : 0.f;
             }
         }
-        // quantities of V(s0) at the own points
-        static_for<0, S>([&](auto sc) {
-            if (decltype(sc)::value != s0) return;
-#pragma unroll
-            for (int k = 0; k < PPT; ++k)
-                if (ts.e[k] >= 0) own_quant(ts, k, sc);
-        });
         if (first) {
             for (int idx = first_item(tid, nth, 0); idx < (t.npe + 1) * WL; idx += nth) {
                 const int b = idx / WL, w = idx - b * WL;
@@ -1029,11 +1038,9 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const ProbDev& P,
         // A: own quantities of V(s), halo fill of stage s
         if (own_active) {
             rt.each([&](int tid, TS<C>& ts) {
-                if (s > s0) {
 #pragma unroll
-                    for (int k = 0; k < PPT; ++k)
-                        if (ts.e[k] >= 0) own_quant(ts, k, sc);
-                }
+                for (int k = 0; k < PPT; ++k)
+                    if (ts.e[k] >= 0) own_quant(ts, k, sc);
                 for (int idx = first_item(tid, nth, s + 2); idx < 2 * t.npe * H; idx += nth) {
                     const int side_idx = idx / H, h = idx - side_idx * H;
                     const int k = side_idx >> 1, side = side_idx & 1;
@@ -1169,11 +1176,18 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const ProbDev& P,
                     float lvn[F];
 #pragma unroll
                     for (int f = 0; f < F; ++f) {
-                        L.wR[s][f][wp] = K[f];
-                        LR acc = LR(TB::a(s + 1, 0)) * L.wR[0][f][wp];
-#pragma unroll
-                        for (int i = 1; i <= s; ++i)
-                            if (TB::a(s + 1, i) != 0.0) acc += LR(TB::a(s + 1, i)) * L.wR[i][f][wp];
+                        if constexpr (rk_keeps_stage_rhs<S>()) L.wR[s][f][wp] = K[f];
+                        // sum_{i <= s} a_{s+1,i} R_i, ascending i, zero coefficients skipped
+                        LR acc = LR(0);
+                        bool have = false;
+                        static_for<0, s + 1>([&](auto ic) {
+                            constexpr int i = decltype(ic)::value;
+                            if constexpr (TB::a(s + 1, i) != 0.0) {
+                                const LR r = i == s ? K[f] : L.wR[i][f][wp];
+                                acc = have ? acc + LR(TB::a(s + 1, i)) * r : LR(TB::a(s + 1, i)) * r;
+                                have = true;
+                            }
+                        });
                         hv[f] = L.wu[f][wp];
                         if constexpr (C::F32) {
                             const float lo = L.wulo[f][wp] + float(dt) * acc;

@@ -7,8 +7,8 @@
 
 namespace atk {
 // points-per-thread classes of each kind: small (default tiles) and large (big PEs)
-constexpr int ppt_small(int kind) { return (kind == K_ADR || kind == K_WSCAL) ? 4 : 2; }
-constexpr int ppt_large(int kind) { return (kind == K_ADR || kind == K_WSCAL) ? 8 : 4; }
+constexpr int ppt_small(int kind) { return kind == K_ADR ? 8 : kind == K_WSCAL ? 4 : 2; }
+constexpr int ppt_large(int kind) { return kind == K_ADR ? 16 : kind == K_WSCAL ? 8 : 4; }
 }  // namespace atk
 
 #define AT_VARIANTS_P(X, K, H, S, F32) X(K, H, S, F32, atk::ppt_small(K)) X(K, H, S, F32, atk::ppt_large(K))
