@@ -164,6 +164,11 @@ int make_plan(const at_problem_desc* probs, int n_probs, const at_run_opts* opts
         pi.J = levels_of(d.scheme, d.mode, d.at_levels);
         pi.D = d.mode == AT_SYNC ? 1 : d.kmax + pi.J;
         pi.st_elems = (int64_t)pi.F * d.n;
+        if (pi.st_elems >= ((int64_t)1 << 31)) {
+            err = fmt("problem %d: F x N = %lld state elements exceed the 32-bit index range", b,
+                      (long long)pi.st_elems);
+            return AT_EUNSUPPORTED;
+        }
         pi.pe_base = plan.total_pes;
         plan.total_points += d.n;
         plan.total_pes += d.p;
@@ -352,6 +357,17 @@ void fill_probdev(const Plan& plan, int b, unsigned char* base, ProbDev& P, int6
     P.kappa = d.pde == AT_PDE_REACTIVE_NS ? d.mu * d.gamma / ((d.gamma - 1.0) * d.pr) : 0.0;
     P.rhoD = d.pde == AT_PDE_REACTIVE_NS ? d.mu / (d.pr * d.le) : 0.0;
     P.eps = d.weno_eps;
+    // scalar FD kind: -c d/dx + alpha d2/dx2 as one stencil on differences u_{i+-o} - u_i
+    // (the central weights sum to zero), coefficients of o = 1..H
+    for (int o = 0; o < 4; ++o) P.lin_p[o] = P.lin_m[o] = 0.0;
+    if (d.scheme != AT_WENO5) {
+        const int H = halo_of(d.scheme);
+        for (int o = 1; o <= H; ++o) {
+            const double a1 = fd_c1(H, o) * P.inv_dx, a2 = fd_c2(H, o) * P.inv_dx2;
+            P.lin_p[o - 1] = -d.c * a1 + d.alpha * a2;
+            P.lin_m[o - 1] = d.c * a1 + d.alpha * a2;
+        }
+    }
     int S;
     rk_tableau(d.rk, &S, P.a, P.bw);
     for (int w = 0; w < 2; ++w) {

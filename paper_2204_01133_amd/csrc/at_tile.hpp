@@ -78,6 +78,7 @@ struct ProbDev {
     double c, alpha, r, gamma, q, ea, b, mu, kappa, rhoD, eps;
     double a[MAXS][MAXS];
     double bw[MAXS];
+    double lin_p[4], lin_m[4];   // scalar FD kind: weights of u_{i+o} - u_i and u_{i-o} - u_i
     // memory (device addresses; host addresses in the emulation)
     void* st_hi[2];          // state ping-pong: F x N (FP64 value or FP32 hi)
     void* st_lo[2];          // FP32 forms: lo parts
@@ -105,6 +106,8 @@ struct PhysP {
     int pde;
     double c, alpha, r, gamma, q, ea, b, mu, kappa, rhoD, eps, inv_dx, inv_dx2, dt;
     float cf, alphaf, rf, inv_dxf, inv_dx2f;     // FP32 copies for the FP32 forms
+    double lp[4], lm[4];                           // scalar FD kind: combined stencil
+    float lpf[4], lmf[4];
 };
 
 #if defined(__HIP_DEVICE_COMPILE__)
@@ -345,6 +348,12 @@ template <> struct FD<3> {   // unused (WENO); keeps templates well-formed
     AT_HD static constexpr double c1(int) { return 0.0; }
     AT_HD static constexpr double c2(int) { return 0.0; }
 };
+AT_HD inline double fd_c1(int H, int o) {
+    return H == 1 ? FD<1>::c1(o) : H == 2 ? FD<2>::c1(o) : H == 4 ? FD<4>::c1(o) : 0.0;
+}
+AT_HD inline double fd_c2(int H, int o) {
+    return H == 1 ? FD<1>::c2(o) : H == 2 ? FD<2>::c2(o) : H == 4 ? FD<4>::c2(o) : 0.0;
+}
 
 // ---------------------------------------------------------------------------
 // physics helpers
@@ -632,23 +641,32 @@ AT_HD AT_FI void rhs_at(const QV<C>& L, const PhysP& P, int64_t e, const typenam
                         typename C::lreal* K) {
     using LR = typename C::lreal;
     if constexpr (C::KIND == K_ADR) {
+        // -c u_x + alpha u_xx as one central stencil on differences to the centre
+        // (the weights of each derivative sum to zero); FP32 forms: hi and lo
+        // differences taken separately (hi - hi exact for neighbouring values)
         if constexpr (C::HILO) {
             const float hc = L.g[0][e], lc = L.glo[e];
-            float s1 = 0.f, s2 = 0.f;
+            float k = 0.f;
+#pragma unroll
             for (int o = 1; o <= C::H; ++o) {
-                const float hp = L.g[0][e + o], hm = L.g[0][e - o];
-                const float lp = L.glo[e + o], lm = L.glo[e - o];
-                s1 += float(FD<C::H>::c1(o)) * ((hp - hm) + (lp - lm));
-                s2 += float(FD<C::H>::c2(o)) * (((hp - hc) + (lp - lc)) + ((hm - hc) + (lm - lc)));
+                const float dp = (L.g[0][e + o] - hc) + (L.glo[e + o] - lc);
+                const float dm = (L.g[0][e - o] - hc) + (L.glo[e - o] - lc);
+                k += P.lpf[o - 1] * dp;
+                k += P.lmf[o - 1] * dm;
             }
-            float k = -P.cf * (s1 * P.inv_dxf) + P.alphaf * (s2 * P.inv_dx2f);
             if (P.pde == PDE_ADR_LOGISTIC) {
                 const float u = hc + lc;
                 k += P.rf * u * (1.f - u);
             }
             K[0] = k;
         } else {
-            LR k = -LR(P.c) * (d1<C>(L.g[0], e) * LR(P.inv_dx)) + LR(P.alpha) * (d2<C>(L.g[0], e) * LR(P.inv_dx2));
+            const LR uc = L.g[0][e];
+            LR k = LR(0);
+#pragma unroll
+            for (int o = 1; o <= C::H; ++o) {
+                k += LR(P.lp[o - 1]) * (L.g[0][e + o] - uc);
+                k += LR(P.lm[o - 1]) * (L.g[0][e - o] - uc);
+            }
             if (P.pde == PDE_ADR_LOGISTIC) k += LR(P.r) * (LR)q[0] * (LR(1) - (LR)q[0]);
             K[0] = k;
         }
@@ -729,6 +747,12 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const ProbDev& P,
     PP.inv_dx = uni(P.inv_dx); PP.inv_dx2 = uni(P.inv_dx2); PP.dt = uni(P.dt);
     PP.cf = (float)PP.c; PP.alphaf = (float)PP.alpha; PP.rf = (float)PP.r;
     PP.inv_dxf = (float)PP.inv_dx; PP.inv_dx2f = (float)PP.inv_dx2;
+    if constexpr (C::KIND == K_ADR) {
+        for (int o = 0; o < H; ++o) {
+            PP.lp[o] = uni(P.lin_p[o]); PP.lm[o] = uni(P.lin_m[o]);
+            PP.lpf[o] = (float)PP.lp[o]; PP.lmf[o] = (float)PP.lm[o];
+        }
+    }
     // memory of the problem (uniform)
     const int64_t Pp = uni((int64_t)P.p);
     const int Dring = uni(P.D);
@@ -836,13 +860,22 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const ProbDev& P,
         {   // all loads first (registers), then the LDS stores
             LR vh[PPT + 1][F];
             float vl[PPT + 1][F];
+            // the range wraps round the periodic domain only in a problem's first and last tile
+            const bool wraps = t.lo < SH || t.lo + t.npts + SH > N;
+            const int Ni = (int)N, xs = (int)t.lo - SH;
 #pragma unroll
             for (int k = 0; k <= PPT; ++k) {
                 const int r = tid + k * nth;
                 if (r >= nraw) continue;
-                int64_t x = t.lo - SH + r;
-                if (x < 0) x = N >= SH ? x + N : wrapi(x, N);
-                else if (x >= N) x = N >= SH ? x - N : wrapi(x, N);
+                int x = xs + r;
+                if (wraps) {
+                    if (Ni >= SH) {
+                        x = x < 0 ? x + Ni : x;
+                        x = x >= Ni ? x - Ni : x;
+                    } else {
+                        x = (int)wrapi(x, N);
+                    }
+                }
 #pragma unroll
                 for (int f = 0; f < F; ++f) {
                     vh[k][f] = st[f * N + x];
@@ -928,16 +961,17 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const ProbDev& P,
     });
     rt.sync();
 
-    // tile-local PE of own point i: the PE owning global x is floor(((x+1) P - 1) / N);
-    // estimated in double as floor((x+1) P/N - 1e-9) (off by at most one for huge N)
-    // and corrected against the tile's PE offsets
-    const double PoverN = (double)Pp / (double)N;
+    // tile-local PE of own point i.  The PE owning global x = lo + i is ceil(z) - 1 with
+    // z = (x + 1) P / N.  In FP32, z' = (i + 1) (P/N) + (lo P/N - pe0) is within 1e-4 of
+    // z (z - pe0 <= npe <= 256, i < 4096), so floor(z' - 1e-3) is the PE or the one
+    // before it; one comparison with the next PE offset decides.
+    const float pn_f = (float)((double)Pp / (double)N);
+    const float pe_c0 = (float)((double)t.lo * ((double)Pp / (double)N) - (double)t.pe0);
     auto pe_local = [&](int i) -> int {
-        const int64_t x = t.lo + i;
-        int pl = (int)((int64_t)((double)(x + 1) * PoverN - 1e-9) - t.pe0);
+        int pl = (int)floorf(fmaf((float)(i + 1), pn_f, pe_c0) - 1e-3f);
         pl = pl < 0 ? 0 : (pl >= t.npe ? t.npe - 1 : pl);
-        if (L.pelo[pl] > i) --pl;
-        else if (L.pelo[pl + 1] <= i) ++pl;
+        if (L.pelo[pl + 1] <= i) ++pl;
+        AT_CHECK(L.pelo[pl] <= i && i < L.pelo[pl + 1], "own point PE", i, pl);
         return pl;
     };
 
@@ -970,7 +1004,7 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const ProbDev& P,
 #pragma unroll
         for (int f = 0; f < F; ++f) q[f] = own_state(ts, k, f, sc, vlo[f]);
         if constexpr (C::HILO) {
-            L.main.g[0][e] = ts.uh[k][0];
+            if (decltype(sc)::value == s0) L.main.g[0][e] = ts.uh[k][0];   // hi: fixed within the step
             L.main.glo[e] = vlo[0];
         } else {
             put_quant<C>(L.main, PP, e, q);

@@ -47,7 +47,7 @@ def single_cases():
         ("fd4_set3", W.adv_diff_c1(n=256, p=8, kmax=2, cdf=W.delay_cdf(W.DELAY_SETS["set3"])), 40),
         ("fd4_as", W.adv_diff_c1(n=256, p=8, kmax=3, mode="as"), 40),
         ("fd4_sync", W.adv_diff_c1(n=256, p=8, kmax=3, mode="sync"), 40),
-        ("fd4_bigpe", W.adv_diff_c1(n=4096, p=2, kmax=2), 10),
+        ("fd4_bigpe", W.adv_diff_c1(n=8192, p=2, kmax=2), 10),
         ("burgers_p8", W.burgers_sweep(128, p=8, n_ref=128), 30),
         ("burgers_onept", W.burgers_sweep(64, p=None, n_ref=64), 20),
         ("advection_e1", W.advection_e1(64, p=4), 20),

@@ -175,7 +175,7 @@ def test_api_errors(torch):
         s.rk_stage(1)                      # stage buffers not reserved
     with pytest.raises(ATError):
         solver([pr.replace(n=10, p=20, q0=np.zeros((1, 10)))])   # P > N
-    big = W.adv_diff_c1(n=4096, p=1)
+    big = W.adv_diff_c1(n=16384, p=1)
     with pytest.raises(ATError) as ei:
         solver([big])                      # PE larger than a tile
     assert ei.value.code == -2
