@@ -27,6 +27,7 @@ struct at_ctx {
     std::vector<uint8_t> state_set;
     std::vector<int64_t> ov_step0, ov_n;
     std::vector<ProbDev> pd;
+    std::vector<ProbDev> tpd_pm, tpd_bt;   // per-tile descriptor copies (host staging)
     int num_cus = 256;
     // graph of graph_steps batched steps
     hipGraphExec_t gexec = nullptr;
@@ -99,6 +100,14 @@ int upload_probs(at_ctx* c) {
         fill_probdev(c->plan, (int)b, c->ws, c->pd[b], c->ov_step0[b], c->ov_n[b]);
     HIPCHK(c, hipMemcpyAsync(c->ws + c->plan.off_probs, c->pd.data(), sizeof(ProbDev) * c->pd.size(),
                              hipMemcpyHostToDevice, c->stream));
+    for (int w = 0; w < 2; ++w) {
+        const std::vector<Tile>& tl = w ? c->plan.tiles_bt : c->plan.tiles_pm;
+        std::vector<ProbDev>& tp = w ? c->tpd_bt : c->tpd_pm;
+        tp.resize(tl.size());
+        for (size_t i = 0; i < tl.size(); ++i) tp[i] = c->pd[tl[i].prob];
+        HIPCHK(c, hipMemcpyAsync(c->ws + (w ? c->plan.off_tpd_bt : c->plan.off_tpd_pm), tp.data(),
+                                 sizeof(ProbDev) * tp.size(), hipMemcpyHostToDevice, c->stream));
+    }
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return AT_OK;
 }
@@ -116,6 +125,7 @@ int batched_step_launches(at_ctx* c, const int64_t* step_ptr, int64_t step_off) 
     for (const Group& g : c->plan.groups) {
         KArgs a = base_args(c, g);
         a.tiles = (const Tile*)(c->ws + c->plan.off_tiles_bt) + g.t0;
+        a.tprobs = (const ProbDev*)(c->ws + c->plan.off_tpd_bt) + g.t0;
         a.ntiles = g.ntiles;
         a.step_ptr = step_ptr;
         a.step_off = step_off;
@@ -265,6 +275,7 @@ int at_step(at_ctx* c, int n_steps) {
                 const int off = cls ? pi.ntiles_small : 0;
                 const int cnt = cls ? pi.ntiles - pi.ntiles_small : pi.ntiles_small;
                 a.tiles = (const Tile*)(c->ws + c->plan.off_tiles_pm) + pi.t0 + off;
+                a.tprobs = (const ProbDev*)(c->ws + c->plan.off_tpd_pm) + pi.t0 + off;
                 a.ntiles = cnt;
                 a.step_off = c->step;
                 a.s_begin = 0;
@@ -319,6 +330,7 @@ int at_rk_stage(at_ctx* c, int stage) {
     for (const Group& g : c->plan.groups) {
         KArgs a = base_args(c, g);
         a.tiles = (const Tile*)(c->ws + c->plan.off_tiles_bt) + g.t0;
+        a.tprobs = (const ProbDev*)(c->ws + c->plan.off_tpd_bt) + g.t0;
         a.ntiles = g.ntiles;
         a.step_off = c->step;
         a.s_begin = stage - 1;

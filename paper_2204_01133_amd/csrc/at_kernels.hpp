@@ -27,7 +27,8 @@ __device__ __forceinline__ int xcd_item(int it, int n) {
 }
 
 template <class C>
-__global__ __launch_bounds__(BLOCK) void at_tile_kernel(KArgs a) {
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(C::WAVES_PER_EU)))
+void at_tile_kernel(KArgs a) {
     extern __shared__ __align__(16) unsigned char lds[];
     GpuRT<C> rt;
     const int64_t n = (a.step_ptr ? *a.step_ptr : 0) + a.step_off;
@@ -35,7 +36,7 @@ __global__ __launch_bounds__(BLOCK) void at_tile_kernel(KArgs a) {
     for (int it = blockIdx.x; it < a.ntiles; it += gridDim.x) {
         const int ti = remap ? xcd_item(it, a.ntiles) : it;
         const Tile t = a.tiles[ti];
-        tile_step<C>(rt, a, t, a.probs[t.prob], n, lds);
+        tile_step<C>(rt, a, t, a.tprobs[ti], n, lds);
         __syncthreads();
     }
 }

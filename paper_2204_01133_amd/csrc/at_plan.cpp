@@ -157,7 +157,8 @@ int make_plan(const at_problem_desc* probs, int n_probs, const at_run_opts* opts
         double a[MAXS][MAXS], bw[MAXS];
         rk_tableau(d.rk, &S, a, bw);
         const int kind = kind_of(d.pde, d.scheme);
-        pi.key = VariantKey{kind, halo_of(d.scheme), S, d.precision != AT_FP64, ppt_small(kind)};
+        const bool f32 = d.precision != AT_FP64;
+        pi.key = VariantKey{kind, halo_of(d.scheme), S, f32, ppt_small(kind, f32)};
         pi.F = fields_of(d.pde);
         pi.H = pi.key.H;
         pi.S = S;
@@ -184,7 +185,7 @@ int make_plan(const at_problem_desc* probs, int n_probs, const at_run_opts* opts
         const at_problem_desc& d = plan.desc[b];
         ProbInfo& pi = plan.info[b];
         VariantKey ks = pi.key, kl = pi.key;
-        kl.ppt = ppt_large(pi.key.kind);
+        kl.ppt = ppt_large(pi.key.kind, pi.key.f32);
         const int tsmall = BLOCK * ks.ppt, tlarge = BLOCK * kl.ppt;
         const int target = plan.opts.tile_points > 0 ? std::min(plan.opts.tile_points, tsmall) : tsmall;
         Tile cur{b, 0, 0, 0, 0};
@@ -253,7 +254,7 @@ int make_plan(const at_problem_desc* probs, int n_probs, const at_run_opts* opts
     for (int b = 0; b < n_probs; ++b) {
         ProbInfo& pi = plan.info[b];
         VariantKey kl = pi.key;
-        kl.ppt = ppt_large(pi.key.kind);
+        kl.ppt = ppt_large(pi.key.kind, pi.key.f32);
         pi.gid[0] = pi.ntiles_small ? group_of(pi.key) : -1;
         pi.gid[1] = pi.ntiles > pi.ntiles_small ? group_of(kl) : -1;
         gtiles.resize(plan.groups.size());
@@ -293,6 +294,8 @@ int make_plan(const at_problem_desc* probs, int n_probs, const at_run_opts* opts
     plan.off_probs = o; o = align256(o + sizeof(ProbDev) * (size_t)n_probs);
     plan.off_tiles_pm = o; o = align256(o + sizeof(Tile) * plan.tiles_pm.size());
     plan.off_tiles_bt = o; o = align256(o + sizeof(Tile) * plan.tiles_bt.size());
+    plan.off_tpd_pm = o; o = align256(o + sizeof(ProbDev) * plan.tiles_pm.size());
+    plan.off_tpd_bt = o; o = align256(o + sizeof(ProbDev) * plan.tiles_bt.size());
     plan.off_step = o; o = align256(o + 64);
     plan.state_bytes_per_step = 0;
     plan.strip_bytes_per_step = 0;

@@ -57,7 +57,9 @@ struct Plan {
     std::vector<Tile> tiles_bt;      // group-major, cost-sorted (batched form)
     std::vector<Group> groups;
     // workspace
-    size_t off_probs, off_tiles_pm, off_tiles_bt, off_step, total;
+    // off_tpd_*: one copy of its problem's descriptor per tile (same order as the tile
+    // lists), so that a workgroup reads its tile and descriptor in one round trip
+    size_t off_probs, off_tiles_pm, off_tiles_bt, off_tpd_pm, off_tpd_bt, off_step, total;
     int64_t total_points, total_pes;
     int64_t state_bytes_per_step, strip_bytes_per_step;
     int max_jmax;

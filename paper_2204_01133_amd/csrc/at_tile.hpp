@@ -165,6 +165,7 @@ AT_HD constexpr bool rk_keeps_stage_rhs() {
 struct KArgs {
     const Tile* tiles;
     const ProbDev* probs;
+    const ProbDev* tprobs;    // descriptor of the problem of tiles[i] at tprobs[i]
     const int64_t* step_ptr;  // device step counter (graph replays), may be null
     int64_t step_off;
     int32_t ntiles, npts_max, npe_max, jmax;
@@ -192,6 +193,9 @@ struct Cfg {
     using lreal = typename std::conditional<F32_, float, double>::type;   // LDS values, K
     using qreal = typename std::conditional<F32_ && !KI::T64, float, double>::type;  // quantities
     static constexpr int WL = 2 * S_ * H_;                      // boundary window length
+    // occupancy target of the kernel (waves per SIMD; 1 = the compiler's choice): the
+    // 8-point FP32 scalar FD kernel is held to 128 VGPRs (4 waves) instead of ~140 (3)
+    static constexpr int WAVES_PER_EU = (KIND_ == K_ADR && F32_ && PPT_ == 8) ? 4 : 1;
 };
 
 AT_HD AT_FI int64_t align16(int64_t b) { return (b + 15) & ~int64_t(15); }
@@ -404,7 +408,8 @@ struct TS {
     int e[C::PPT];                                // ext index of the own point (-1: none)
     typename C::lreal uh[C::PPT][C::F];           // u^n (FP64 value / FP32 hi)
     float ul[C::PPT][C::F];                       // FP32 lo
-    typename C::lreal K[C::S][C::PPT][C::F];      // stage right-hand sides
+    typename C::lreal K[C::S][C::PPT][C::F];      // stage right-hand sides (each dies after its last use)
+    typename C::lreal acc[C::PPT][C::F];          // sum_s b_s K_s so far (s ascending)
 };
 
 // views of one set of differentiated quantities (main region or one window parity)
@@ -955,7 +960,11 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const ProbDev& P,
                 for (int s = 0; s < S; ++s)
                     if (s < s0)
 #pragma unroll
-                        for (int f = 0; f < F; ++f) ts.K[s][k][f] = kb[((int64_t)s * F + f) * N + x];
+                        for (int f = 0; f < F; ++f) {
+                            ts.K[s][k][f] = kb[((int64_t)s * F + f) * N + x];
+                            ts.acc[k][f] = s == 0 ? LR(TB::b(0)) * ts.K[s][k][f]
+                                                  : ts.acc[k][f] + LR(TB::b(s)) * ts.K[s][k][f];
+                        }
             }
         }
     });
@@ -983,10 +992,17 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const ProbDev& P,
             if constexpr (C::F32) return (Q)ts.uh[k][f] + (Q)ts.ul[k][f];
             else return (Q)ts.uh[k][f];
         } else {
-            LR acc = LR(TB::a(s, 0)) * ts.K[0][k][f];
-#pragma unroll
-            for (int i = 1; i < s; ++i)
-                if (TB::a(s, i) != 0.0) acc += LR(TB::a(s, i)) * ts.K[i][k][f];
+            // sum_{i<s} a_si K_i, i ascending; zero coefficients are skipped at compile
+            // time so that a K_i no later stage needs is not kept in registers
+            LR acc = LR(0);
+            bool have = false;
+            static_for<0, s>([&](auto ic) {
+                constexpr int i = decltype(ic)::value;
+                if constexpr (TB::a(s, i) != 0.0) {
+                    acc = have ? acc + LR(TB::a(s, i)) * ts.K[i][k][f] : LR(TB::a(s, i)) * ts.K[i][k][f];
+                    have = true;
+                }
+            });
             if constexpr (C::F32) {
                 const float lo = ts.ul[k][f] + float(dt) * acc;
                 vlo = lo;
@@ -1188,7 +1204,16 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const ProbDev& P,
                     LR K[F];
                     rhs_at<C>(L.main, PP, e, q, K);
 #pragma unroll
-                    for (int f = 0; f < F; ++f) ts.K[s][k][f] = K[f];
+                    for (int f = 0; f < F; ++f) {
+                        ts.K[s][k][f] = K[f];
+                        ts.acc[k][f] = s == 0 ? LR(TB::b(0)) * K[f] : ts.acc[k][f] + LR(TB::b(s)) * K[f];
+                    }
+                    if (stage_io && s == s1 && s1 < S - 1) {   // per-stage entry point: K_s out
+                        const View<LR> kb{(LR*)P.kbuf, P.kbuf_len};
+                        const int64_t x = t.lo + tid + k * nth;
+#pragma unroll
+                        for (int f = 0; f < F; ++f) kb[((int64_t)s * F + f) * N + x] = K[f];
+                    }
                 }
             }
             if (win_active) {
@@ -1255,23 +1280,12 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const ProbDev& P,
         for (int k = 0; k < PPT; ++k) {
             if (ts.e[k] < 0) continue;
             const int64_t x = t.lo + tid + k * nth;
-            if (s1 < S - 1) {
-                const View<LR> kb{(LR*)P.kbuf, P.kbuf_len};
-                static_for<0, S>([&](auto sc) {
-                    constexpr int s = decltype(sc)::value;
-                    if (s != s1) return;
-#pragma unroll
-                    for (int f = 0; f < F; ++f) kb[((int64_t)s * F + f) * N + x] = ts.K[s][k][f];
-                });
-                continue;
-            }
+            if (s1 < S - 1) continue;              // per-stage entry point: K_s1 already out
             const View<LR> dst = st_view<C>(P, nxt);
             const View<float> dlo = lo_view(P, nxt, C::F32);
 #pragma unroll
             for (int f = 0; f < F; ++f) {
-                LR acc = LR(TB::b(0)) * ts.K[0][k][f];
-#pragma unroll
-                for (int s = 1; s < S; ++s) acc += LR(TB::b(s)) * ts.K[s][k][f];
+                const LR acc = ts.acc[k][f];       // sum_s b_s K_s, s ascending
                 if constexpr (C::F32) {
                     // compensated update: (hi, lo) + dt*acc, TwoSum of hi and (lo + dt*acc)
                     const float hi = ts.uh[k][f];

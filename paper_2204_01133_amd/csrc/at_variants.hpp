@@ -6,12 +6,17 @@
 #include "at_tile.hpp"
 
 namespace atk {
-// points-per-thread classes of each kind: small (default tiles) and large (big PEs)
-constexpr int ppt_small(int kind) { return kind == K_ADR ? 8 : kind == K_WSCAL ? 4 : 2; }
-constexpr int ppt_large(int kind) { return kind == K_ADR ? 16 : kind == K_WSCAL ? 8 : 4; }
+// points-per-thread classes of each kind and precision: small (default tiles) and
+// large (big PEs).  The FP32 scalar FD kind takes 8 points per thread (its state is
+// half the registers of FP64); its large class holds PEs of up to 4096 points.
+constexpr int ppt_small(int kind, bool f32) {
+    return kind == K_ADR ? (f32 ? 8 : 4) : kind == K_WSCAL ? 4 : 2;
+}
+constexpr int ppt_large(int kind, bool f32) { return kind == K_ADR ? 16 : 2 * ppt_small(kind, f32); }
 }  // namespace atk
 
-#define AT_VARIANTS_P(X, K, H, S, F32) X(K, H, S, F32, atk::ppt_small(K)) X(K, H, S, F32, atk::ppt_large(K))
+#define AT_VARIANTS_P(X, K, H, S, F32) \
+    X(K, H, S, F32, atk::ppt_small(K, F32)) X(K, H, S, F32, atk::ppt_large(K, F32))
 #define AT_VARIANTS_SF(X, K, H) \
     AT_VARIANTS_P(X, K, H, 1, 0) AT_VARIANTS_P(X, K, H, 2, 0) AT_VARIANTS_P(X, K, H, 3, 0) \
     AT_VARIANTS_P(X, K, H, 4, 0) AT_VARIANTS_P(X, K, H, 1, 1) AT_VARIANTS_P(X, K, H, 2, 1) \
