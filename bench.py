@@ -35,7 +35,7 @@ HBM_PEAK_GBS = 8000.0
 # sources that decide the headline kernel's code and its tiles (the traffic record
 # is used only while their hash matches the one it was measured with)
 KERNEL_SOURCES = ["paper_2204_01133_amd/csrc/at_tile.hpp", "paper_2204_01133_amd/csrc/at_kernels.hpp",
-                  "paper_2204_01133_amd/csrc/at_variants.hpp", "paper_2204_01133_amd/csrc/at_k_adr.hip",
+                  "paper_2204_01133_amd/csrc/at_variants.hpp", "paper_2204_01133_amd/csrc/at_k_adr32.hip",
                   "paper_2204_01133_amd/csrc/at_plan.cpp", "paper_2204_01133_amd/csrc/at_plan.hpp"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "c3_fp32c_traffic.json")
 

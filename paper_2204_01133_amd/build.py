@@ -21,7 +21,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(BUILD, "libat.so")
 EMU = os.path.join(BUILD, "libat_emu.so")
 
-HIP_SOURCES = ["at_api.hip", "at_k_adr.hip", "at_k_rns.hip", "at_k_wscal.hip", "at_k_eul.hip",
+HIP_SOURCES = ["at_api.hip", "at_k_adr.hip", "at_k_adr32.hip", "at_k_rns.hip", "at_k_rns32.hip", "at_k_wscal.hip", "at_k_eul.hip",
                "at_k_reul.hip"]
 HOST_SOURCES = ["at_plan.cpp"]
 
@@ -57,7 +57,7 @@ def build_lib(jobs: int = 8) -> str:
 def build_emu() -> str:
     os.makedirs(BUILD, exist_ok=True)
     tmp = EMU + f".tmp{os.getpid()}"
-    _run(["g++", "-std=c++17", "-O2", "-g", "-fPIC", "-shared", "-Wall", "-Wno-unused-variable",
+    _run(["g++", "-std=c++17", "-O1", "-fPIC", "-shared", "-Wall", "-Wno-unused-variable",
           "-Wno-maybe-uninitialized", "-o", tmp, os.path.join(CSRC, "at_emu.cpp"),
           os.path.join(CSRC, "at_plan.cpp")])
     os.replace(tmp, EMU)

@@ -75,7 +75,8 @@ __global__ void k_add_step(int64_t* d, int64_t v) { *d += v; }
 int launch_key(at_ctx* c, const VariantKey& k, const KArgs& a, int grid) {
     if (grid <= 0 || a.ntiles <= 0) return AT_OK;
     hipError_t e = hipSuccess;
-    bool ok = launch_adr(k, a, grid, c->stream, &e) || launch_rns(k, a, grid, c->stream, &e) ||
+    bool ok = launch_adr(k, a, grid, c->stream, &e) || launch_adr32(k, a, grid, c->stream, &e) ||
+              launch_rns(k, a, grid, c->stream, &e) || launch_rns32(k, a, grid, c->stream, &e) ||
               launch_wscal(k, a, grid, c->stream, &e) || launch_eul(k, a, grid, c->stream, &e) ||
               launch_reul(k, a, grid, c->stream, &e);
     if (!ok) return fail(c, AT_EUNSUPPORTED, "kernel variant not compiled");

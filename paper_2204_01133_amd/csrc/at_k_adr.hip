@@ -1,3 +1,3 @@
 // Tile-kernel instantiations of one kernel kind (compiled as its own unit).
 #include "at_kernels.hpp"
-AT_DEFINE_LAUNCHER(launch_adr, AT_VARIANTS_ADR)
+AT_DEFINE_LAUNCHER(launch_adr, AT_VARIANTS_ADR64)

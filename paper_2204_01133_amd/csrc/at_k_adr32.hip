@@ -1,0 +1,3 @@
+// Tile-kernel instantiations of one kernel kind (compiled as its own unit).
+#include "at_kernels.hpp"
+AT_DEFINE_LAUNCHER(launch_adr32, AT_VARIANTS_ADR32)

@@ -16,7 +16,17 @@ struct GpuRT {
     __device__ int nthreads() const { return (int)blockDim.x; }
     template <class Fn>
     __device__ void each(Fn&& f) { f((int)threadIdx.x, ts); }
-    __device__ void sync() { __syncthreads(); }
+    // Workgroup barrier for LDS traffic only: the wave's own LDS operations are complete
+    // (lgkmcnt(0)) before the barrier, and the compiler moves no memory operation across
+    // it.  Unlike __syncthreads() it does not wait for the wave's global loads and stores
+    // (vmcnt): no phase reads global memory that another wave of the workgroup wrote in
+    // the same launch.
+    __device__ void sync() {
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        __builtin_amdgcn_s_waitcnt(0xC07F);   // gfx9 encoding: lgkmcnt(0), vmcnt/expcnt unconstrained
+        __builtin_amdgcn_s_barrier();
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    }
 };
 
 // Work item order with consecutive items on one XCD: workgroup i runs on XCD
@@ -37,7 +47,7 @@ void at_tile_kernel(KArgs a) {
         const int ti = remap ? xcd_item(it, a.ntiles) : it;
         const Tile t = a.tiles[ti];
         tile_step<C>(rt, a, t, a.tprobs[ti], n, lds);
-        __syncthreads();
+        if (it + (int)gridDim.x < a.ntiles) rt.sync();   // LDS reused by the next tile
     }
 }
 
@@ -56,7 +66,9 @@ hipError_t launch_variant(const KArgs& a, int grid, hipStream_t s) {
 
 // per-kind dispatchers (one translation unit each); return false if the key is not theirs
 bool launch_adr(const VariantKey& k, const KArgs& a, int grid, hipStream_t s, hipError_t* e);
+bool launch_adr32(const VariantKey& k, const KArgs& a, int grid, hipStream_t s, hipError_t* e);
 bool launch_rns(const VariantKey& k, const KArgs& a, int grid, hipStream_t s, hipError_t* e);
+bool launch_rns32(const VariantKey& k, const KArgs& a, int grid, hipStream_t s, hipError_t* e);
 bool launch_wscal(const VariantKey& k, const KArgs& a, int grid, hipStream_t s, hipError_t* e);
 bool launch_eul(const VariantKey& k, const KArgs& a, int grid, hipStream_t s, hipError_t* e);
 bool launch_reul(const VariantKey& k, const KArgs& a, int grid, hipStream_t s, hipError_t* e);

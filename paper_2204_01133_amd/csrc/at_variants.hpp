@@ -17,14 +17,20 @@ constexpr int ppt_large(int kind, bool f32) { return kind == K_ADR ? 16 : 2 * pp
 
 #define AT_VARIANTS_P(X, K, H, S, F32) \
     X(K, H, S, F32, atk::ppt_small(K, F32)) X(K, H, S, F32, atk::ppt_large(K, F32))
-#define AT_VARIANTS_SF(X, K, H) \
-    AT_VARIANTS_P(X, K, H, 1, 0) AT_VARIANTS_P(X, K, H, 2, 0) AT_VARIANTS_P(X, K, H, 3, 0) \
-    AT_VARIANTS_P(X, K, H, 4, 0) AT_VARIANTS_P(X, K, H, 1, 1) AT_VARIANTS_P(X, K, H, 2, 1) \
-    AT_VARIANTS_P(X, K, H, 3, 1) AT_VARIANTS_P(X, K, H, 4, 1)
+#define AT_VARIANTS_S(X, K, H, F32) \
+    AT_VARIANTS_P(X, K, H, 1, F32) AT_VARIANTS_P(X, K, H, 2, F32) AT_VARIANTS_P(X, K, H, 3, F32) \
+    AT_VARIANTS_P(X, K, H, 4, F32)
+#define AT_VARIANTS_SF(X, K, H) AT_VARIANTS_S(X, K, H, 0) AT_VARIANTS_S(X, K, H, 1)
 
-#define AT_VARIANTS_ADR(X) AT_VARIANTS_SF(X, atk::K_ADR, 1) AT_VARIANTS_SF(X, atk::K_ADR, 2) \
-    AT_VARIANTS_SF(X, atk::K_ADR, 4)
-#define AT_VARIANTS_RNS(X) AT_VARIANTS_SF(X, atk::K_RNS, 2) AT_VARIANTS_SF(X, atk::K_RNS, 4)
+// the FD kinds in two units each (FP64 / FP32 forms) to halve their compile time
+#define AT_VARIANTS_ADR64(X) AT_VARIANTS_S(X, atk::K_ADR, 1, 0) AT_VARIANTS_S(X, atk::K_ADR, 2, 0) \
+    AT_VARIANTS_S(X, atk::K_ADR, 4, 0)
+#define AT_VARIANTS_ADR32(X) AT_VARIANTS_S(X, atk::K_ADR, 1, 1) AT_VARIANTS_S(X, atk::K_ADR, 2, 1) \
+    AT_VARIANTS_S(X, atk::K_ADR, 4, 1)
+#define AT_VARIANTS_ADR(X) AT_VARIANTS_ADR64(X) AT_VARIANTS_ADR32(X)
+#define AT_VARIANTS_RNS64(X) AT_VARIANTS_S(X, atk::K_RNS, 2, 0) AT_VARIANTS_S(X, atk::K_RNS, 4, 0)
+#define AT_VARIANTS_RNS32(X) AT_VARIANTS_S(X, atk::K_RNS, 2, 1) AT_VARIANTS_S(X, atk::K_RNS, 4, 1)
+#define AT_VARIANTS_RNS(X) AT_VARIANTS_RNS64(X) AT_VARIANTS_RNS32(X)
 #define AT_VARIANTS_WSCAL(X) AT_VARIANTS_SF(X, atk::K_WSCAL, 3)
 #define AT_VARIANTS_EUL(X) AT_VARIANTS_SF(X, atk::K_EUL, 3)
 #define AT_VARIANTS_REUL(X) AT_VARIANTS_SF(X, atk::K_REUL, 3)
