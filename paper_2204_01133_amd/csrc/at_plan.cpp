@@ -165,8 +165,9 @@ int make_plan(const at_problem_desc* probs, int n_probs, const at_run_opts* opts
         pi.J = levels_of(d.scheme, d.mode, d.at_levels);
         pi.D = d.mode == AT_SYNC ? 1 : d.kmax + pi.J;
         pi.st_elems = (int64_t)pi.F * d.n;
-        if (pi.st_elems >= ((int64_t)1 << 31)) {
-            err = fmt("problem %d: F x N = %lld state elements exceed the 32-bit index range", b,
+        // the kernels address each array with 32-bit offsets: every array under 4 GiB
+        if (pi.st_elems * (int64_t)MAXS * 8 >= ((int64_t)1 << 32)) {
+            err = fmt("problem %d: F x N = %lld state elements exceed the 32-bit offset range", b,
                       (long long)pi.st_elems);
             return AT_EUNSUPPORTED;
         }
@@ -312,6 +313,11 @@ int make_plan(const at_problem_desc* probs, int n_probs, const at_run_opts* opts
         int64_t lds;
         variant_sizes(pi.key, 1, 1, 1, &lds, &pi.rec_bytes);
         pi.ring_bytes = (int64_t)pi.D * d.p * 2 * pi.rec_bytes;
+        if (pi.ring_bytes >= ((int64_t)1 << 32)) {
+            err = fmt("problem %d: strip ring of %lld bytes exceeds the 32-bit offset range", b,
+                      (long long)pi.ring_bytes);
+            return AT_EUNSUPPORTED;
+        }
         pi.off_ring = o; o = align256(o + (size_t)pi.ring_bytes);
         pi.kbuf_len = plan.opts.stage_api ? (int64_t)pi.S * pi.st_elems : 0;
         pi.off_kbuf = o; o = align256(o + sl * (size_t)pi.kbuf_len);

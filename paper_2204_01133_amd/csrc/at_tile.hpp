@@ -67,6 +67,43 @@ struct View {
     }
 };
 
+// Global-memory element access.  On the GPU the pointer is taken in the global
+// address space, so the compiler emits global (not flat) loads and stores: flat
+// operations also count against the LDS wait counter that every barrier drains.
+// Indices are 32-bit unsigned (the planner keeps every array under 4 GiB), so with a
+// uniform base the address is the scalar base plus a 32-bit vector offset (one VGPR,
+// not a 64-bit address pair per access).
+#if defined(__HIP_DEVICE_COMPILE__)
+template <class T>
+__device__ __forceinline__ T gld(const T* p, uint32_t i) {
+    return ((const __attribute__((address_space(1))) T*)p)[i];
+}
+template <class T>
+__device__ __forceinline__ void gst(T* p, uint32_t i, T v) {
+    ((__attribute__((address_space(1))) T*)p)[i] = v;
+}
+#else
+template <class T>
+inline T gld(const T* p, uint32_t i) { return p[i]; }
+template <class T>
+inline void gst(T* p, uint32_t i, T v) { p[i] = v; }
+#endif
+
+// Bounds-checked (emulation) view of a global array.
+template <class T>
+struct GView {
+    T* p;
+    int64_t n;
+    AT_HD AT_FI T ld(int64_t i) const {
+        AT_CHECK(i >= 0 && i < n, "global view", i, n);
+        return gld(p, (uint32_t)i);
+    }
+    AT_HD AT_FI void st(int64_t i, T v) const {
+        AT_CHECK(i >= 0 && i < n, "global view", i, n);
+        gst(p, (uint32_t)i, v);
+    }
+};
+
 // Device-resident description of one problem (built by the planner).
 struct ProbDev {
     int64_t n;
@@ -131,6 +168,49 @@ inline int uni(int v) { return v; }
 inline double uni(double v) { return v; }
 inline int64_t uni(int64_t v) { return v; }
 #endif
+
+template <class T>
+AT_HD AT_FI T* uni_ptr(T* p) { return (T*)(uintptr_t)uni((int64_t)(uintptr_t)p); }
+
+// A register copy of a problem descriptor whose every field is known to be the same
+// across the workgroup (scalar registers on the GPU): read once at the start of a
+// tile, so no later access goes back to memory.  Its arrays are only ever indexed with
+// compile-time indices (a run-time index would put the copy in scratch memory), so the
+// delay thresholds cdf, which the delay draw indexes at run time, are not copied.
+AT_HD AT_FI ProbDev uniform_copy(const ProbDev& P) {
+    ProbDev u;
+    u.n = uni(P.n);
+    u.p = uni(P.p); u.pde = uni(P.pde); u.mode = uni(P.mode); u.gran = uni(P.gran);
+    u.kmax = uni(P.kmax); u.J = uni(P.J); u.D = uni(P.D); u.n_cdf = uni(P.n_cdf);
+    u.keep_lo = uni(P.keep_lo); u.S = uni(P.S); u.F = uni(P.F);
+    u.seed = (uint64_t)uni((int64_t)P.seed);
+    u.pid = uni(P.pid);
+    u.dt = uni(P.dt); u.inv_dx = uni(P.inv_dx); u.inv_dx2 = uni(P.inv_dx2);
+    u.c = uni(P.c); u.alpha = uni(P.alpha); u.r = uni(P.r); u.gamma = uni(P.gamma);
+    u.q = uni(P.q); u.ea = uni(P.ea); u.b = uni(P.b); u.mu = uni(P.mu);
+    u.kappa = uni(P.kappa); u.rhoD = uni(P.rhoD); u.eps = uni(P.eps);
+    for (int i = 0; i < MAXS; ++i) {
+        for (int j = 0; j < MAXS; ++j) u.a[i][j] = uni(P.a[i][j]);
+        u.bw[i] = uni(P.bw[i]);
+    }
+    for (int i = 0; i < 4; ++i) {
+        u.lin_p[i] = uni(P.lin_p[i]);
+        u.lin_m[i] = uni(P.lin_m[i]);
+    }
+    for (int w = 0; w < 2; ++w) {
+        u.st_hi[w] = uni_ptr(P.st_hi[w]);
+        u.st_lo[w] = uni_ptr(P.st_lo[w]);
+    }
+    u.ring = uni_ptr(P.ring);
+    u.rec_bytes = uni(P.rec_bytes);
+    u.kbuf = uni_ptr(P.kbuf);
+    u.ov = uni_ptr(P.ov);
+    u.ov_step0 = uni(P.ov_step0); u.ov_n = uni(P.ov_n);
+    u.log_drawn = uni_ptr(P.log_drawn); u.log_eff = uni_ptr(P.log_eff);
+    u.log_cap = uni(P.log_cap);
+    u.kbuf_len = uni(P.kbuf_len);
+    return u;
+}
 
 // Butcher tableaus (eq. rk1) fixed by the stage count of the supported schemes:
 // S = 1 forward Euler, 2 Heun (eq. rk2), 3 SSP-RK3, 4 classical RK4.
@@ -705,11 +785,11 @@ AT_HD AT_FI void rhs_at(const QV<C>& L, const PhysP& P, int64_t e, const typenam
 // global memory helpers
 // ---------------------------------------------------------------------------
 template <class C>
-AT_HD AT_FI View<typename C::lreal> st_view(const ProbDev& P, int which) {
-    return View<typename C::lreal>{(typename C::lreal*)P.st_hi[which], (int64_t)C::F * P.n};
+AT_HD AT_FI GView<typename C::lreal> st_view(const ProbDev& P, int which) {
+    return GView<typename C::lreal>{(typename C::lreal*)(which ? P.st_hi[1] : P.st_hi[0]), (int64_t)C::F * P.n};
 }
-AT_HD AT_FI View<float> lo_view(const ProbDev& P, int which, bool f32) {
-    return View<float>{(float*)P.st_lo[which], f32 ? (int64_t)P.F * P.n : 0};
+AT_HD AT_FI GView<float> lo_view(const ProbDev& P, int which, bool f32) {
+    return GView<float>{(float*)(which ? P.st_lo[1] : P.st_lo[0]), f32 ? (int64_t)P.F * P.n : 0};
 }
 
 
@@ -730,8 +810,9 @@ template <class C>
 AT_HD AT_FI int64_t ring_lo_off(int s, int h, int f) { return (int64_t)C::H * C::F + ((int64_t)s * C::H + h) * C::F + f; }
 
 template <class C, class RT>
-AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const ProbDev& P, int64_t n_in,
+AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const ProbDev& P_in, int64_t n_in,
                      unsigned char* lds_base) {
+    const ProbDev P = uniform_copy(P_in);
     using LR = typename C::lreal;
     using Q = typename C::qreal;
     constexpr int F = C::F, H = C::H, S = C::S, PPT = C::PPT, WL = C::WL, NQ = C::NQ;
@@ -778,8 +859,8 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const ProbDev& P,
     const bool first = s0 == 0;
     const bool stage_io = (a.flags & KF_STAGE_IO) != 0;
     const int cur = (int)(n & 1), nxt = cur ^ 1;
-    const View<LR> st = st_view<C>(P, cur);
-    const View<float> stlo = lo_view(P, cur, C::F32);
+    const GView<LR> st = st_view<C>(P, cur);
+    const GView<float> stlo = lo_view(P, cur, C::F32);
     const bool use_lo = C::F32 && P.keep_lo;
     const int64_t N = uni(P.n);
     const int J = uni(P.J);
@@ -791,28 +872,30 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const ProbDev& P,
     // strip ring: slot of level n (levels n - d, 0 <= d < D, are slot_n - d mod D),
     // records of the tile's PEs at a slot are 2 * npe consecutive records
     const int slot_n = uni((int)(n % Dring));
-    const int64_t slot_stride = Pp * 2 * recb;
-    unsigned char* const ring_tile = ring + (int64_t)t.pe0 * 2 * recb;
-    // record of PE (t.pe0 + k), side, at level n - d
-    auto rec_back = [&](int d, int k, int side) -> unsigned char* {
+    // ring element offsets (in 4-byte words from the ring base; the ring is under 4 GiB)
+    const uint32_t slot_stride_w = (uint32_t)(Pp * 2 * recb / 4);
+    const uint32_t recw = (uint32_t)(recb / 4);
+    const uint32_t ring_tile_w = (uint32_t)((int64_t)t.pe0 * 2 * recb / 4);
+    const float* const ring_f = (const float*)ring;
+    // first word of the record of PE (t.pe0 + k), side, at level n - d
+    auto rec_back = [&](int d, int k, int side) -> uint32_t {
         AT_CHECK(d >= 0 && d < Dring, "ring depth", d, Dring);
         int slot = slot_n - d;
         if (slot < 0) slot += Dring;
         const int64_t idx = ((int64_t)slot * Pp + t.pe0 + k) * 2 + side;
         AT_CHECK(idx >= 0 && idx < (int64_t)Dring * Pp * 2, "ring record", idx, (int64_t)Dring * Pp * 2);
-        return ring_tile + (int64_t)slot * slot_stride + (int64_t)(2 * k + side) * recb;
+        return ring_tile_w + (uint32_t)slot * slot_stride_w + (uint32_t)(2 * k + side) * recw;
     };
-    unsigned char* const ring_n = ring_tile + (int64_t)slot_n * slot_stride;
+    const uint32_t ring_n_w = ring_tile_w + (uint32_t)slot_n * slot_stride_w;
     // ring record of PE (t.pe0 + k), side, level n: stage s at halo point h
     auto rec_store = [&](int k, int side, int s, int h, int f, LR v, float hi) {
         AT_CHECK(k >= 0 && k < t.npe, "ring store", k, t.npe);
-        unsigned char* rec = ring_n + (int64_t)(2 * k + side) * recb;
+        const uint32_t w0 = ring_n_w + (uint32_t)(2 * k + side) * recw;
         if constexpr (C::F32) {
-            float* rf = (float*)rec;
-            rf[ring_lo_off<C>(s, h, f)] = v;
-            if (s == 0) rf[h * F + f] = hi;
+            gst((float*)ring, w0 + (uint32_t)ring_lo_off<C>(s, h, f), (float)v);
+            if (s == 0) gst((float*)ring, w0 + (uint32_t)(h * F + f), hi);
         } else {
-            ((double*)rec)[((int64_t)s * H + h) * F + f] = v;
+            gst((double*)ring, w0 / 2 + (uint32_t)(((int64_t)s * H + h) * F + f), (double)v);
         }
     };
     // write the window's synchronous-stage strip value at window position w of boundary b
@@ -833,13 +916,13 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const ProbDev& P,
         if (P.ov && n >= P.ov_step0 && n < P.ov_step0 + P.ov_n) {
             const int64_t oi = ((n - P.ov_step0) * P.p + pe) * 2 + side;
             AT_CHECK(oi >= 0 && oi < P.ov_n * P.p * 2, "override", oi, P.ov_n * P.p * 2);
-            kd = P.ov[oi];
+            kd = gld(P.ov, (uint32_t)oi);
         } else if (P.gran == G_PE) {
-            kd = draw_delay(P, dprefix, pe, 0);
+            kd = draw_delay(P_in, dprefix, pe, 0);
         } else if (P.gran == G_PE_SIDE) {
-            kd = draw_delay(P, dprefix, pe, side);
+            kd = draw_delay(P_in, dprefix, pe, side);
         } else {
-            kd = draw_delay(P, dprefix, side == 0 ? pe : (pe + 1 == P.p ? 0 : pe + 1), 0);
+            kd = draw_delay(P_in, dprefix, side == 0 ? pe : (pe + 1 == P.p ? 0 : pe + 1), 0);
         }
         int ke;
         if (P.mode == M_AT) {
@@ -883,8 +966,8 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const ProbDev& P,
                 }
 #pragma unroll
                 for (int f = 0; f < F; ++f) {
-                    vh[k][f] = st[f * N + x];
-                    vl[k][f] = use_lo ? stlo[f * N + x] : 0.f;
+                    vh[k][f] = st.ld(f * N + x);
+                    vl[k][f] = use_lo ? stlo.ld(f * N + x) : 0.f;
                 }
             }
 #pragma unroll
@@ -920,26 +1003,26 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const ProbDev& P,
             if ((a.flags & KF_LOG) && first && P.log_drawn) {
                 const int64_t li = (wrapi(n, P.log_cap) * P.p + t.pe0 + k) * 2 + side;
                 AT_CHECK(li >= 0 && li < P.log_cap * P.p * 2, "log", li, P.log_cap * P.p * 2);
-                P.log_drawn[li] = (uint8_t)kd;
-                P.log_eff[li] = (uint8_t)ke;
+                gst(P.log_drawn, (uint32_t)li, (uint8_t)kd);
+                gst(P.log_eff, (uint32_t)li, (uint8_t)ke);
             }
             // delayed strips (and level n in per-stage mode) from the ring
             const int jeff = ke == 0 ? (first ? 0 : 1) : J;
 #pragma unroll
             for (int l = 0; l < JM; ++l) {
                 if (l >= jeff) continue;
-                const unsigned char* rec = rec_back(ke + l, k, side);
+                const uint32_t w0 = rec_back(ke + l, k, side);
                 const int sob = side_idx * L.SOREC + l * nrec;
                 LR v[nrec];
                 float vh[C::F32 ? H * F : 1];
 #pragma unroll
                 for (int r = 0; r < nrec; ++r) {
-                    if constexpr (C::F32) v[r] = ((const float*)rec)[H * F + r];
-                    else v[r] = ((const double*)rec)[r];
+                    if constexpr (C::F32) v[r] = gld(ring_f, w0 + (uint32_t)(H * F + r));
+                    else v[r] = gld((const double*)ring_f, w0 / 2 + (uint32_t)r);
                 }
                 if constexpr (C::F32) {
 #pragma unroll
-                    for (int r = 0; r < H * F; ++r) vh[r] = ((const float*)rec)[r];
+                    for (int r = 0; r < H * F; ++r) vh[r] = gld(ring_f, w0 + (uint32_t)r);
                 }
 #pragma unroll
                 for (int r = 0; r < nrec; ++r) L.SO[sob + r] = v[r];
@@ -950,7 +1033,7 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const ProbDev& P,
             }
         }
         if (stage_io) {
-            const View<LR> kb{(LR*)P.kbuf, P.kbuf_len};
+            const GView<LR> kb{(LR*)P.kbuf, P.kbuf_len};
 #pragma unroll
             for (int k = 0; k < PPT; ++k) {
                 const int i = tid + k * nth;
@@ -961,7 +1044,7 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const ProbDev& P,
                     if (s < s0)
 #pragma unroll
                         for (int f = 0; f < F; ++f) {
-                            ts.K[s][k][f] = kb[((int64_t)s * F + f) * N + x];
+                            ts.K[s][k][f] = kb.ld(((int64_t)s * F + f) * N + x);
                             ts.acc[k][f] = s == 0 ? LR(TB::b(0)) * ts.K[s][k][f]
                                                   : ts.acc[k][f] + LR(TB::b(s)) * ts.K[s][k][f];
                         }
@@ -1209,10 +1292,10 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const ProbDev& P,
                         ts.acc[k][f] = s == 0 ? LR(TB::b(0)) * K[f] : ts.acc[k][f] + LR(TB::b(s)) * K[f];
                     }
                     if (stage_io && s == s1 && s1 < S - 1) {   // per-stage entry point: K_s out
-                        const View<LR> kb{(LR*)P.kbuf, P.kbuf_len};
+                        const GView<LR> kb{(LR*)P.kbuf, P.kbuf_len};
                         const int64_t x = t.lo + tid + k * nth;
 #pragma unroll
-                        for (int f = 0; f < F; ++f) kb[((int64_t)s * F + f) * N + x] = K[f];
+                        for (int f = 0; f < F; ++f) kb.st(((int64_t)s * F + f) * N + x, K[f]);
                     }
                 }
             }
@@ -1281,8 +1364,8 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const ProbDev& P,
             if (ts.e[k] < 0) continue;
             const int64_t x = t.lo + tid + k * nth;
             if (s1 < S - 1) continue;              // per-stage entry point: K_s1 already out
-            const View<LR> dst = st_view<C>(P, nxt);
-            const View<float> dlo = lo_view(P, nxt, C::F32);
+            const GView<LR> dst = st_view<C>(P, nxt);
+            const GView<float> dlo = lo_view(P, nxt, C::F32);
 #pragma unroll
             for (int f = 0; f < F; ++f) {
                 const LR acc = ts.acc[k][f];       // sum_s b_s K_s, s ascending
@@ -1293,10 +1376,10 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const ProbDev& P,
                     const float sum = hi + tt;
                     const float bb = sum - hi;
                     const float err = (hi - (sum - bb)) + (tt - bb);
-                    dst[f * N + x] = sum;
-                    if (P.keep_lo) dlo[f * N + x] = err;
+                    dst.st(f * N + x, sum);
+                    if (P.keep_lo) dlo.st(f * N + x, err);
                 } else {
-                    dst[f * N + x] = ts.uh[k][f] + dt * acc;
+                    dst.st(f * N + x, (LR)(ts.uh[k][f] + dt * acc));
                 }
             }
         }
