@@ -280,6 +280,7 @@ struct Cfg {
 
 AT_HD AT_FI int64_t align16(int64_t b) { return (b + 15) & ~int64_t(15); }
 
+
 constexpr int JMAXW = 8;   // row length of the LDS table of extrapolation weights
 
 // LDS layout of a launch (same function on host and device).
@@ -309,9 +310,11 @@ struct Layout {
         o_rl = o;    o += C::F32 ? align16(C::F * EXR * 4) : 0;
         const int64_t raw_end = o;
         o = 0;
-        o_g = o;     o += align16(C::NQ * EXM * sl);
-        o_glo = o;   o += C::HILO ? align16(EXM * 4) : 0;
-        o_lam = o;   o += C::WENO ? align16(EXM * sl) : 0;
+        // main region, two stage parities (a stage reads one, writes the next stage's
+        // quantities into the other); the FP32 scalar kind shares its hi part
+        o_g = o;     o += align16((C::HILO ? 1 : 2) * C::NQ * EXM * sl);
+        o_glo = o;   o += C::HILO ? align16(2 * EXM * 4) : 0;
+        o_lam = o;   o += C::WENO ? align16(2 * EXM * sl) : 0;
         o_flux = o;  o += C::WENO ? align16(C::F * EXM * sl) : 0;
         if (o < raw_end) o = raw_end;
         // the scalar FD kind's window quantities are its window state (aliased below)
@@ -507,12 +510,12 @@ template <class C>
 struct Lds {
     using L = typename C::lreal;
     static constexpr int SR = C::S > 1 ? C::S - 1 : 1;
-    QV<C> main, win[2];
+    QV<C> main[2], win[2];     // main: stage parities
     View<L> wu[C::F], wq[2][C::F];
     View<float> wulo[C::F];
     View<L> wR[SR][C::F];
-    View<L> SO;
-    View<float> SOhi;
+    View<L> SO;                // delayed strips [side][level][stage][h][f] (FP32: lo parts)
+    View<float> SOhi;          // FP32 forms: hi parts [side][level][h][f]
     View<int> pelo, keff;
     View<double> wt;           // extrapolation weights w_l(k) at [k * JMAXW + l]
     View<L> rh[C::F];          // raw u^n (FP64 value / FP32 hi) on [lo - S*H, lo + npts + S*H)
@@ -521,20 +524,22 @@ struct Lds {
     AT_HD void init(unsigned char* base, const Layout<C>& Lo, int npe_max, int jm) {
         EXM = (int)Lo.EXM; EXW = (int)Lo.EXW; SOREC = (int)Lo.SOREC; jmax = jm;
         const int64_t nm = Lo.EXM, nw = Lo.EXW;
-        for (int q = 0; q < C::NQ; ++q) {
-            main.g[q] = View<L>{(L*)(base + Lo.o_g) + q * nm, nm};
-            for (int par = 0; par < 2; ++par)
-                win[par].g[q] = View<L>{(L*)(base + Lo.o_gw) + (par * C::NQ + q) * nw, nw};
-        }
-        main.glo = View<float>{(float*)(base + Lo.o_glo), C::HILO ? nm : 0};
-        main.lam = View<L>{(L*)(base + Lo.o_lam), C::WENO ? nm : 0};
         for (int par = 0; par < 2; ++par) {
+            const int pg = C::HILO ? 0 : par;
+            for (int q = 0; q < C::NQ; ++q) {
+                main[par].g[q] = View<L>{(L*)(base + Lo.o_g) + (pg * C::NQ + q) * nm, nm};
+                win[par].g[q] = View<L>{(L*)(base + Lo.o_gw) + (par * C::NQ + q) * nw, nw};
+            }
+            main[par].glo = View<float>{(float*)(base + Lo.o_glo) + par * nm, C::HILO ? nm : 0};
+            main[par].lam = View<L>{(L*)(base + Lo.o_lam) + par * nm, C::WENO ? nm : 0};
             win[par].glo = View<float>{(float*)(base + Lo.o_gwlo) + par * nw, C::HILO ? nw : 0};
             win[par].lam = View<L>{(L*)(base + Lo.o_lamw) + par * nw, C::WENO ? nw : 0};
+            for (int f = 0; f < C::F; ++f) {
+                main[par].flux[f] = View<L>{(L*)(base + Lo.o_flux) + f * nm, C::WENO ? nm : 0};
+                win[par].flux[f] = View<L>{(L*)(base + Lo.o_fluxw) + f * nw, C::WENO ? nw : 0};
+            }
         }
         for (int f = 0; f < C::F; ++f) {
-            main.flux[f] = View<L>{(L*)(base + Lo.o_flux) + f * nm, C::WENO ? nm : 0};
-            win[0].flux[f] = win[1].flux[f] = View<L>{(L*)(base + Lo.o_fluxw) + f * nw, C::WENO ? nw : 0};
             wu[f] = View<L>{(L*)(base + Lo.o_wu) + f * nw, nw};
             wulo[f] = View<float>{(float*)(base + Lo.o_wulo) + f * nw, C::F32 ? nw : 0};
             for (int par = 0; par < 2; ++par)
@@ -573,6 +578,7 @@ struct Lds {
 AT_HD AT_FI int first_item(int tid, int nth, int r) {
     return nth == 256 ? ((tid + 256 - 64 * (r & 3)) & 255) : tid;
 }
+
 
 // compile-time loop: f(std::integral_constant<int, I>) for I in [B, E)
 template <int B, int E, class Fn>
@@ -1096,17 +1102,86 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const ProbDev& P_
             }
         }
     };
+    // quantities of V(s) at own slot k, into the main region of stage parity s & 1
     auto own_quant = [&](const TS<C>& ts, int k, auto sc) {
+        constexpr int s = decltype(sc)::value;
+        const QV<C>& M = L.main[s & 1];
         const int e = ts.e[k];
         Q q[F];
         float vlo[F];
 #pragma unroll
         for (int f = 0; f < F; ++f) q[f] = own_state(ts, k, f, sc, vlo[f]);
         if constexpr (C::HILO) {
-            if (decltype(sc)::value == s0) L.main.g[0][e] = ts.uh[k][0];   // hi: fixed within the step
-            L.main.glo[e] = vlo[0];
+            if (s == s0) M.g[0][e] = ts.uh[k][0];   // hi: fixed within the step, both parities
+            M.glo[e] = vlo[0];
         } else {
-            put_quant<C>(L.main, PP, e, q);
+            put_quant<C>(M, PP, e, q);
+        }
+    };
+    // ext position of halo point h on the given side of tile PE k
+    auto halo_e = [&](int k, int side, int h) -> int {
+        const int ebase = L.pelo[k] + 2 * H * k;
+        return side == 0 ? ebase + h : ebase + H + (L.pelo[k + 1] - L.pelo[k]) + h;
+    };
+    // halo point h of a PE side at stage s: the differentiated quantities of the delayed
+    // strips (levels n - ke - l), extrapolated in time to level n with the Lagrange
+    // weights of the delay (per-stage entry point with delay 0: level n's own strip)
+    auto halo_from_so = [&](int side_idx, int h, auto sc) {
+        constexpr int s = decltype(sc)::value;
+        const QV<C>& M = L.main[s & 1];
+        const int e = halo_e(side_idx >> 1, side_idx & 1, h);
+        const int ke = L.keff[side_idx];
+        const int jeff = ke == 0 ? 1 : J;
+        double w[JM];
+#pragma unroll
+        for (int l = 0; l < JM; ++l) w[l] = L.wt[ke * JMAXW + l];
+        const int sob = side_idx * L.SOREC;
+        const int sohb = side_idx * L.jmax;
+        if constexpr (C::HILO) {
+            const float h0 = L.SOhi[((sohb + 0) * H + h) * F];
+            const float l0 = L.SO[sob + ((0 * S + s) * H + h) * F];
+            float lo = l0;
+#pragma unroll
+            for (int l = 1; l < JM; ++l) {
+                if (l >= jeff) continue;
+                const float hl = L.SOhi[((sohb + l) * H + h) * F];
+                const float ll = L.SO[sob + ((l * S + s) * H + h) * F];
+                lo += float(w[l]) * ((hl - h0) + (ll - l0));
+            }
+            if (s == s0) M.g[0][e] = h0;
+            M.glo[e] = lo;
+        } else {
+            Q gl[NQ], g0[NQ], acc[NQ];
+            Q lam0 = Q(0), laml = Q(0);
+#pragma unroll
+            for (int l = 0; l < JM; ++l) {
+                if (l >= jeff) continue;
+                Q q[F];
+#pragma unroll
+                for (int f = 0; f < F; ++f) {
+                    const LR v = L.SO[sob + ((l * S + s) * H + h) * F + f];
+                    if constexpr (C::F32) q[f] = (Q)L.SOhi[((sohb + l) * H + h) * F + f] + (Q)v;
+                    else q[f] = (Q)v;
+                }
+                quant_values<C>(PP, q, gl, laml);
+                if (l == 0) {
+                    lam0 = laml;
+#pragma unroll
+                    for (int j = 0; j < NQ; ++j) {
+                        g0[j] = gl[j];
+                        acc[j] = C::F32 ? gl[j] : Q(w[0]) * gl[j];
+                    }
+                } else {
+#pragma unroll
+                    for (int j = 0; j < NQ; ++j) {
+                        if constexpr (C::F32) acc[j] += Q(w[l]) * (gl[j] - g0[j]);
+                        else acc[j] += Q(w[l]) * gl[j];
+                    }
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < NQ; ++j) M.g[j][e] = (LR)acc[j];
+            if constexpr (C::WENO) M.lam[e] = (LR)lam0;
         }
     };
 
@@ -1159,93 +1234,48 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const ProbDev& P_
     });
     rt.sync();
 
-    // ---- the stages ----------------------------------------------------------------
+    // ---- A0: quantities of the first stage at own and halo points --------------------
+    static_for<0, S>([&](auto sc) {
+        if (decltype(sc)::value != s0) return;
+        rt.each([&](int tid, TS<C>& ts) {
+#pragma unroll
+            for (int k = 0; k < PPT; ++k)
+                if (ts.e[k] >= 0) own_quant(ts, k, sc);
+            for (int idx = first_item(tid, nth, 2); idx < 2 * t.npe * H; idx += nth) {
+                const int side_idx = idx / H, h = idx - side_idx * H;
+                if (first && L.keff[side_idx] == 0) {
+                    // synchronous stage 0 of level n: the window's value at the halo point
+                    const int k = side_idx >> 1, side = side_idx & 1;
+                    const int wp = (k + side) * WL + (S - 1) * H + side * H + h;
+                    const int e = halo_e(k, side, h);
+                    const QV<C>& M = L.main[0];
+#pragma unroll
+                    for (int j = 0; j < NQ; ++j) M.g[j][e] = L.win[0].g[j][wp];
+                    if constexpr (C::HILO) M.glo[e] = L.win[0].glo[wp];
+                    if constexpr (C::WENO) M.lam[e] = L.win[0].lam[wp];
+                } else {
+                    halo_from_so(side_idx, h, sc);
+                }
+            }
+        });
+    });
+    rt.sync();
+
+    // ---- the stages: one phase each (two for WENO) ----------------------------------
+    //   stage s reads the main region of parity s & 1 and writes the quantities of
+    //   stage s + 1 (own points, halo points, windows) into parity (s + 1) & 1
     static_for<0, S>([&](auto sc) {
         constexpr int s = decltype(sc)::value;
+        constexpr int sn = s + 1 < S ? s + 1 : s;                 // next stage (if any)
+        using SN = std::integral_constant<int, sn>;
         const bool own_active = s >= s0 && s <= s1;
+        const bool next_active = s + 1 < S && own_active && s + 1 <= s1;
         const bool win_active = first && s + 1 < S;
         if (!own_active && !win_active) return;
+        const QV<C>& Mc = L.main[s & 1];
+        const QV<C>& Mn = L.main[sn & 1];
         const QV<C>& Wc = L.win[s & 1];
         const QV<C>& Wn = L.win[(s + 1) & 1];
-
-        // A: own quantities of V(s), halo fill of stage s
-        if (own_active) {
-            rt.each([&](int tid, TS<C>& ts) {
-#pragma unroll
-                for (int k = 0; k < PPT; ++k)
-                    if (ts.e[k] >= 0) own_quant(ts, k, sc);
-                for (int idx = first_item(tid, nth, s + 2); idx < 2 * t.npe * H; idx += nth) {
-                    const int side_idx = idx / H, h = idx - side_idx * H;
-                    const int k = side_idx >> 1, side = side_idx & 1;
-                    const int ke = L.keff[side_idx];
-                    const int np = L.pelo[k + 1] - L.pelo[k];
-                    const int ebase = L.pelo[k] + 2 * H * k;
-                    const int e = side == 0 ? ebase + h : ebase + H + np + h;
-                    if (ke == 0 && first) {
-                        // synchronous stage s of level n: the window's value at the halo point
-                        const int wp = (k + side) * WL + (S - 1) * H + side * H + h;
-#pragma unroll
-                        for (int j = 0; j < NQ; ++j) L.main.g[j][e] = Wc.g[j][wp];
-                        if constexpr (C::HILO) L.main.glo[e] = Wc.glo[wp];
-                        if constexpr (C::WENO) L.main.lam[e] = Wc.lam[wp];
-                        continue;
-                    }
-                    const int jeff = ke == 0 ? 1 : J;
-                    double w[JM];
-#pragma unroll
-                    for (int l = 0; l < JM; ++l) w[l] = L.wt[ke * JMAXW + l];
-                    const int sob = side_idx * L.SOREC;
-                    const int sohb = side_idx * L.jmax;
-                    if constexpr (C::HILO) {
-                        const float h0 = L.SOhi[((sohb + 0) * H + h) * F];
-                        const float l0 = L.SO[sob + ((0 * S + s) * H + h) * F];
-                        float lo = l0;
-#pragma unroll
-                        for (int l = 1; l < JM; ++l) {
-                            if (l >= jeff) continue;
-                            const float hl = L.SOhi[((sohb + l) * H + h) * F];
-                            const float ll = L.SO[sob + ((l * S + s) * H + h) * F];
-                            lo += float(w[l]) * ((hl - h0) + (ll - l0));
-                        }
-                        L.main.g[0][e] = h0;
-                        L.main.glo[e] = lo;
-                    } else {
-                        Q gl[NQ], g0[NQ], acc[NQ];
-                        Q lam0 = Q(0), laml = Q(0);
-#pragma unroll
-                        for (int l = 0; l < JM; ++l) {
-                            if (l >= jeff) continue;
-                            Q q[F];
-#pragma unroll
-                            for (int f = 0; f < F; ++f) {
-                                const LR v = L.SO[sob + ((l * S + s) * H + h) * F + f];
-                                if constexpr (C::F32) q[f] = (Q)L.SOhi[((sohb + l) * H + h) * F + f] + (Q)v;
-                                else q[f] = (Q)v;
-                            }
-                            quant_values<C>(PP, q, gl, laml);
-                            if (l == 0) {
-                                lam0 = laml;
-#pragma unroll
-                                for (int j = 0; j < NQ; ++j) {
-                                    g0[j] = gl[j];
-                                    acc[j] = C::F32 ? gl[j] : Q(w[0]) * gl[j];
-                                }
-                            } else {
-#pragma unroll
-                                for (int j = 0; j < NQ; ++j) {
-                                    if constexpr (C::F32) acc[j] += Q(w[l]) * (gl[j] - g0[j]);
-                                    else acc[j] += Q(w[l]) * gl[j];
-                                }
-                            }
-                        }
-#pragma unroll
-                        for (int j = 0; j < NQ; ++j) L.main.g[j][e] = (LR)acc[j];
-                        if constexpr (C::WENO) L.main.lam[e] = (LR)lam0;
-                    }
-                }
-            });
-            rt.sync();
-        }
 
         // B1 (WENO): interface fluxes
         if constexpr (C::WENO) {
@@ -1255,10 +1285,10 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const ProbDev& P_
                     for (int k = 0; k < PPT; ++k) {
                         const int e = ts.e[k];
                         if (e < 0) continue;
-                        iface_flux<C>(L.main, PP, e);              // right interface of the point
+                        iface_flux<C>(Mc, PP, e);                  // right interface of the point
                         // left interface of the PE's first point: its left neighbour is a halo slot
                         const int i = tid + k * nth;
-                        if (L.pelo[pe_local(i)] == i) iface_flux<C>(L.main, PP, e - 1);
+                        if (L.pelo[pe_local(i)] == i) iface_flux<C>(Mc, PP, e - 1);
                     }
                 }
                 if (win_active) {
@@ -1273,7 +1303,8 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const ProbDev& P_
             rt.sync();
         }
 
-        // B2: K_s at own points; R_s and the synchronous stage s+1 on the windows
+        // B2: K_s at own points and the quantities of stage s+1; R_s and the synchronous
+        // stage s+1 on the windows
         rt.each([&](int tid, TS<C>& ts) {
             if (own_active) {
 #pragma unroll
@@ -1285,7 +1316,7 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const ProbDev& P_
 #pragma unroll
                     for (int f = 0; f < F; ++f) q[f] = own_state(ts, k, f, sc, vlo);
                     LR K[F];
-                    rhs_at<C>(L.main, PP, e, q, K);
+                    rhs_at<C>(Mc, PP, e, q, K);
 #pragma unroll
                     for (int f = 0; f < F; ++f) {
                         ts.K[s][k][f] = K[f];
@@ -1296,6 +1327,16 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const ProbDev& P_
                         const int64_t x = t.lo + tid + k * nth;
 #pragma unroll
                         for (int f = 0; f < F; ++f) kb.st(((int64_t)s * F + f) * N + x, K[f]);
+                    }
+                    if constexpr (s + 1 < S)
+                        if (next_active) own_quant(ts, k, SN{});
+                }
+            }
+            if constexpr (s + 1 < S) {
+                if (next_active) {
+                    for (int idx = first_item(tid, nth, s + 3); idx < 2 * t.npe * H; idx += nth) {
+                        const int side_idx = idx / H, h = idx - side_idx * H;
+                        if (!(first && L.keff[side_idx] == 0)) halo_from_so(side_idx, h, SN{});
                     }
                 }
             }
@@ -1351,10 +1392,20 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const ProbDev& P_
                     } else {
                         put_quant<C>(Wn, PP, wp, qn);
                     }
+                    // a halo point of a PE side with delay 0: its stage s+1 quantities
+                    const int h2 = w - (S - 1) * H;
+                    if (next_active && h2 >= 0 && h2 < 2 * H) {
+                        const int side = h2 < H ? 0 : 1, kpe = b - side, h = h2 - side * H;
+                        if (kpe >= 0 && kpe < t.npe && L.keff[2 * kpe + side] == 0) {
+                            const int e = halo_e(kpe, side, h);
+                            if constexpr (C::HILO) Mn.glo[e] = lvn[0];
+                            else put_quant<C>(Mn, PP, e, qn);
+                        }
+                    }
                 }
             }
         });
-        rt.sync();
+        if (s + 1 < S && (next_active || (first && s + 2 < S))) rt.sync();
     });
 
     // ---- P5: the update (or the stage output of the per-stage entry point) ----------
