@@ -274,8 +274,9 @@ struct Cfg {
     using qreal = typename std::conditional<F32_ && !KI::T64, float, double>::type;  // quantities
     static constexpr int WL = 2 * S_ * H_;                      // boundary window length
     // occupancy target of the kernel (waves per SIMD; 1 = the compiler's choice): the
-    // 8-point FP32 scalar FD kernel is held to 128 VGPRs (4 waves) instead of ~140 (3)
-    static constexpr int WAVES_PER_EU = (KIND_ == K_ADR && F32_ && PPT_ == 8) ? 4 : 1;
+    // small-tile scalar FD kernels (8 points per thread in FP32, 6 in FP64) are held to
+    // 128 VGPRs (4 waves) instead of ~160 (3)
+    static constexpr int WAVES_PER_EU = (KIND_ == K_ADR && PPT_ == (F32_ ? 8 : 6)) ? 4 : 1;
 };
 
 AT_HD AT_FI int64_t align16(int64_t b) { return (b + 15) & ~int64_t(15); }

@@ -7,10 +7,11 @@
 
 namespace atk {
 // points-per-thread classes of each kind and precision: small (default tiles) and
-// large (big PEs).  The FP32 scalar FD kind takes 8 points per thread (its state is
-// half the registers of FP64); its large class holds PEs of up to 4096 points.
+// large (big PEs).  The scalar FD kind takes 8 points per thread in the FP32 forms and
+// 6 in FP64 (its state is twice the registers); its large class holds PEs of up to
+// 4096 points.
 constexpr int ppt_small(int kind, bool f32) {
-    return kind == K_ADR ? (f32 ? 8 : 4) : kind == K_WSCAL ? 4 : 2;
+    return kind == K_ADR ? (f32 ? 8 : 6) : kind == K_WSCAL ? 4 : 2;
 }
 constexpr int ppt_large(int kind, bool f32) { return kind == K_ADR ? 16 : 2 * ppt_small(kind, f32); }
 }  // namespace atk
