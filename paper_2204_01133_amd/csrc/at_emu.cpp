@@ -83,7 +83,10 @@ static void run_group(EmuCtx& c, const Group& g, int s_begin, int s_end, int fla
         std::memset(lds.data(), 0xff, lds.size());
         CpuRT<C> rt;
         const Tile& t = a.tiles[ti];
-        tile_step<C>(rt, a, t, a.probs[t.prob], c.step, lds.data());
+        if (s_begin == 0 && s_end == C::S - 1 && !(flags & KF_STAGE_IO))
+            tile_step<C, true>(rt, a, t, a.probs[t.prob], c.step, lds.data());
+        else
+            tile_step<C, false>(rt, a, t, a.probs[t.prob], c.step, lds.data());
     }
 }
 

@@ -36,7 +36,7 @@ __device__ __forceinline__ int xcd_item(int it, int n) {
     return x * q + (x < r ? x : r) + j;
 }
 
-template <class C>
+template <class C, bool STEP>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(C::WAVES_PER_EU)))
 void at_tile_kernel(KArgs a) {
     extern __shared__ __align__(16) unsigned char lds[];
@@ -46,22 +46,30 @@ void at_tile_kernel(KArgs a) {
     for (int it = blockIdx.x; it < a.ntiles; it += gridDim.x) {
         const int ti = remap ? xcd_item(it, a.ntiles) : it;
         const Tile t = a.tiles[ti];
-        tile_step<C>(rt, a, t, a.tprobs[ti], n, lds);
+        tile_step<C, STEP>(rt, a, t, a.tprobs[ti], n, lds);
         if (it + (int)gridDim.x < a.ntiles) rt.sync();   // LDS reused by the next tile
     }
 }
 
-template <class C>
-hipError_t launch_variant(const KArgs& a, int grid, hipStream_t s) {
+template <class C, bool STEP>
+hipError_t launch_form(const KArgs& a, int grid, hipStream_t s) {
     static bool attr_done = false;
     if (!attr_done) {
-        hipError_t e = hipFuncSetAttribute((const void*)at_tile_kernel<C>,
+        hipError_t e = hipFuncSetAttribute((const void*)at_tile_kernel<C, STEP>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         if (e != hipSuccess) return e;
         attr_done = true;
     }
-    hipLaunchKernelGGL(at_tile_kernel<C>, dim3(grid), dim3(BLOCK), (size_t)a.lds_bytes, s, a);
+    hipLaunchKernelGGL((at_tile_kernel<C, STEP>), dim3(grid), dim3(BLOCK), (size_t)a.lds_bytes, s, a);
     return hipGetLastError();
+}
+
+// whole steps take the kernel whose stage range is fixed at compile time
+template <class C>
+hipError_t launch_variant(const KArgs& a, int grid, hipStream_t s) {
+    if (a.s_begin == 0 && a.s_end == C::S - 1 && !(a.flags & KF_STAGE_IO))
+        return launch_form<C, true>(a, grid, s);
+    return launch_form<C, false>(a, grid, s);
 }
 
 // per-kind dispatchers (one translation unit each); return false if the key is not theirs

@@ -816,7 +816,9 @@ AT_HD AT_FI GView<float> lo_view(const ProbDev& P, int which, bool f32) {
 template <class C>
 AT_HD AT_FI int64_t ring_lo_off(int s, int h, int f) { return (int64_t)C::H * C::F + ((int64_t)s * C::H + h) * C::F + f; }
 
-template <class C, class RT>
+// STEP: the launch is a whole step (stages 0..S-1, no stage inputs or outputs), so the
+// stage range is known at compile time; otherwise it is read from the arguments.
+template <class C, bool STEP, class RT>
 AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const ProbDev& P_in, int64_t n_in,
                      unsigned char* lds_base) {
     const ProbDev P = uniform_copy(P_in);
@@ -862,9 +864,11 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const ProbDev& P_
 
 
     const int nth = rt.nthreads();
-    const int s0 = a.s_begin, s1 = a.s_end;
-    const bool first = s0 == 0;
-    const bool stage_io = (a.flags & KF_STAGE_IO) != 0;
+    const int s0 = STEP ? 0 : a.s_begin, s1 = STEP ? S - 1 : a.s_end;
+    const bool first = STEP || s0 == 0;
+    const bool stage_io = !STEP && (a.flags & KF_STAGE_IO) != 0;
+    AT_CHECK(!STEP || (a.s_begin == 0 && a.s_end == S - 1 && !(a.flags & KF_STAGE_IO)), "whole step",
+             a.s_begin, a.s_end);
     const int cur = (int)(n & 1), nxt = cur ^ 1;
     const GView<LR> st = st_view<C>(P, cur);
     const GView<float> stlo = lo_view(P, cur, C::F32);
