@@ -15,7 +15,14 @@ struct GpuRT {
     TS<C> ts;
     __device__ int nthreads() const { return (int)blockDim.x; }
     template <class Fn>
-    __device__ void each(Fn&& f) { f((int)threadIdx.x, ts); }
+    __device__ void each(Fn&& f) {
+        // the thread index is opaque to the optimiser in each phase, so that values
+        // derived from it are computed where they are used instead of being hoisted
+        // out of the tile loop and held in registers across every phase
+        int tid = (int)threadIdx.x;
+        __asm__ volatile("" : "+v"(tid));
+        f(tid, ts);
+    }
     // Workgroup barrier for LDS traffic only: the wave's own LDS operations are complete
     // (lgkmcnt(0)) before the barrier, and the compiler moves no memory operation across
     // it.  Unlike __syncthreads() it does not wait for the wave's global loads and stores
