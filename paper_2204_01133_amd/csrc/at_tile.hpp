@@ -953,12 +953,56 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const ProbDev& P_
     //   PE offsets, delays, delayed strips of the ring, stage inputs (per-stage mode)
     constexpr int SH = S * H;
     const double invP = 1.0 / (double)Pp;
+    constexpr int nrec = S * H * F;              // lo (FP32) or value (FP64) words of a level
+    constexpr int nhi = C::F32 ? H * F : 1;      // FP32 hi words of a level
+    // levels of the first PE side loaded before the raw range is stored (one in FP64,
+    // whose records take twice the registers)
+    constexpr int JPF = C::F32 ? 0 : 1;
+    constexpr int JPR = JPF > 0 ? JPF : 1;
+    // delays of a PE side (into LDS, and the log); the number of ring levels it reads
+    auto side_delays = [&](int side_idx, int& ke) -> int {
+        const int k = side_idx >> 1, side = side_idx & 1;
+        int kd;
+        ke = delays_of(k, side, kd);
+        L.keff[side_idx] = ke;
+        if ((a.flags & KF_LOG) && first && P.log_drawn) {
+            const int64_t li = (wrapi(n, P.log_cap) * P.p + t.pe0 + k) * 2 + side;
+            AT_CHECK(li >= 0 && li < P.log_cap * P.p * 2, "log", li, P.log_cap * P.p * 2);
+            gst(P.log_drawn, (uint32_t)li, (uint8_t)kd);
+            gst(P.log_eff, (uint32_t)li, (uint8_t)ke);
+        }
+        // delayed strips (and level n in per-stage mode) from the ring
+        return ke == 0 ? (first ? 0 : 1) : J;
+    };
+    auto ring_ld = [&](int side_idx, int ke, int l, LR (&v)[nrec], float (&vh)[nhi]) {
+        const uint32_t w0 = rec_back(ke + l, side_idx >> 1, side_idx & 1);
+#pragma unroll
+        for (int r = 0; r < nrec; ++r) {
+            if constexpr (C::F32) v[r] = gld(ring_f, w0 + (uint32_t)(H * F + r));
+            else v[r] = gld((const double*)ring_f, w0 / 2 + (uint32_t)r);
+        }
+        if constexpr (C::F32) {
+#pragma unroll
+            for (int r = 0; r < H * F; ++r) vh[r] = gld(ring_f, w0 + (uint32_t)r);
+        }
+    };
+    auto ring_put = [&](int side_idx, int l, const LR (&v)[nrec], const float (&vh)[nhi]) {
+        const int sob = side_idx * L.SOREC + l * nrec;
+#pragma unroll
+        for (int r = 0; r < nrec; ++r) L.SO[sob + r] = v[r];
+        if constexpr (C::F32) {
+#pragma unroll
+            for (int r = 0; r < H * F; ++r) L.SOhi[(side_idx * L.jmax + l) * H * F + r] = vh[r];
+        }
+    };
     rt.each([&](int tid, TS<C>& ts) {
         const int nraw = t.npts + 2 * SH;
         AT_CHECK(nraw <= nth * (PPT + 1), "raw range", nraw, nth * (PPT + 1));
-        {   // all loads first (registers), then the LDS stores
-            LR vh[PPT + 1][F];
-            float vl[PPT + 1][F];
+        // loads of the raw range and of the first PE side's ring levels are all issued
+        // before any of them is stored, so that their latencies overlap
+        LR vh[PPT + 1][F];
+        float vl[PPT + 1][F];
+        {
             // the range wraps round the periodic domain only in a problem's first and last tile
             const bool wraps = t.lo < SH || t.lo + t.npts + SH > N;
             const int Ni = (int)N, xs = (int)t.lo - SH;
@@ -981,16 +1025,17 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const ProbDev& P_
                     vl[k][f] = use_lo ? stlo.ld(f * N + x) : 0.f;
                 }
             }
+        }
+        const int si0 = first_item(tid, nth, 1);
+        const bool has0 = si0 < 2 * t.npe;
+        LR rv[JPR][nrec];
+        float rvh[JPR][nhi];
+        int jeff0 = 0, ke0 = 0;
+        if (has0) {
+            jeff0 = side_delays(si0, ke0);
 #pragma unroll
-            for (int k = 0; k <= PPT; ++k) {
-                const int r = tid + k * nth;
-                if (r >= nraw) continue;
-#pragma unroll
-                for (int f = 0; f < F; ++f) {
-                    L.rh[f][r] = vh[k][f];
-                    if constexpr (C::F32) L.rl[f][r] = vl[k][f];
-                }
-            }
+            for (int l = 0; l < JPF; ++l)
+                if (l < jeff0) ring_ld(si0, ke0, l, rv[l], rvh[l]);
         }
         for (int k = first_item(tid, nth, 3); k <= t.npe; k += nth) {
             // floor(p N / P) of PE p = pe0 + k: estimated in double, then corrected exactly
@@ -1005,42 +1050,40 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const ProbDev& P_
             const int k = tid / JMAXW, l = tid % JMAXW;
             L.wt[tid] = l < JM ? WTAB.w[k == 0 ? 1 : J][k][l] : 0.0;
         }
-        constexpr int nrec = S * H * F;
-        for (int side_idx = first_item(tid, nth, 1); side_idx < 2 * t.npe; side_idx += nth) {
-            const int k = side_idx >> 1, side = side_idx & 1;
-            int kd;
-            const int ke = delays_of(k, side, kd);
-            L.keff[side_idx] = ke;
-            if ((a.flags & KF_LOG) && first && P.log_drawn) {
-                const int64_t li = (wrapi(n, P.log_cap) * P.p + t.pe0 + k) * 2 + side;
-                AT_CHECK(li >= 0 && li < P.log_cap * P.p * 2, "log", li, P.log_cap * P.p * 2);
-                gst(P.log_drawn, (uint32_t)li, (uint8_t)kd);
-                gst(P.log_eff, (uint32_t)li, (uint8_t)ke);
+#pragma unroll
+        for (int k = 0; k <= PPT; ++k) {
+            const int r = tid + k * nth;
+            if (r >= nraw) continue;
+#pragma unroll
+            for (int f = 0; f < F; ++f) {
+                L.rh[f][r] = vh[k][f];
+                if constexpr (C::F32) L.rl[f][r] = vl[k][f];
             }
-            // delayed strips (and level n in per-stage mode) from the ring
-            const int jeff = ke == 0 ? (first ? 0 : 1) : J;
+        }
+        if (has0) {
+#pragma unroll
+            for (int l = 0; l < JPF; ++l)
+                if (l < jeff0) ring_put(si0, l, rv[l], rvh[l]);
+#pragma unroll
+            for (int l = JPF; l < JM; ++l) {
+                if (l >= jeff0) continue;
+                LR v[nrec];
+                float vh[nhi];
+                ring_ld(si0, ke0, l, v, vh);
+                ring_put(si0, l, v, vh);
+            }
+        }
+        // further PE sides (tiles of more than nth / 2 PEs)
+        for (int side_idx = si0 + nth; side_idx < 2 * t.npe; side_idx += nth) {
+            int ke;
+            const int jeff = side_delays(side_idx, ke);
 #pragma unroll
             for (int l = 0; l < JM; ++l) {
                 if (l >= jeff) continue;
-                const uint32_t w0 = rec_back(ke + l, k, side);
-                const int sob = side_idx * L.SOREC + l * nrec;
                 LR v[nrec];
-                float vh[C::F32 ? H * F : 1];
-#pragma unroll
-                for (int r = 0; r < nrec; ++r) {
-                    if constexpr (C::F32) v[r] = gld(ring_f, w0 + (uint32_t)(H * F + r));
-                    else v[r] = gld((const double*)ring_f, w0 / 2 + (uint32_t)r);
-                }
-                if constexpr (C::F32) {
-#pragma unroll
-                    for (int r = 0; r < H * F; ++r) vh[r] = gld(ring_f, w0 + (uint32_t)r);
-                }
-#pragma unroll
-                for (int r = 0; r < nrec; ++r) L.SO[sob + r] = v[r];
-                if constexpr (C::F32) {
-#pragma unroll
-                    for (int r = 0; r < H * F; ++r) L.SOhi[(side_idx * L.jmax + l) * H * F + r] = vh[r];
-                }
+                float vh[nhi];
+                ring_ld(side_idx, ke, l, v, vh);
+                ring_put(side_idx, l, v, vh);
             }
         }
         if (stage_io) {
