@@ -44,6 +44,7 @@ struct CpuRT {
         for (int t = 0; t < BLOCK; ++t) f(t, ts[t]);
     }
     void sync() {}
+    void sync_mem() {}
 };
 
 struct EmuCtx {

@@ -34,6 +34,9 @@ struct GpuRT {
         __builtin_amdgcn_s_barrier();
         __atomic_signal_fence(__ATOMIC_SEQ_CST);
     }
+    // Barrier that also drains the wave's vector-memory operations (vmcnt(0)): after
+    // direct global-to-LDS copies, which complete on that counter.
+    __device__ void sync_mem() { __syncthreads(); }
 };
 
 // Work item order with consecutive items on one XCD: workgroup i runs on XCD

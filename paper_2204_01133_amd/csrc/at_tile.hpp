@@ -89,6 +89,28 @@ template <class T>
 inline void gst(T* p, uint32_t i, T v) { p[i] = v; }
 #endif
 
+// Direct global-to-LDS copy of one 32-bit word per lane: lane j of a wave writes word
+// j of the wave's LDS block, whose base must be the same across the wave (the LDS
+// address register of the instruction is per wave).  The copy holds no register and
+// completes on the vector-memory counter, so the barrier after it must drain that
+// counter too.  On the host the lane writes its word directly.
+#if defined(__HIP_DEVICE_COMPILE__)
+__device__ __forceinline__ void lds_copy_word(float* lds_wave, int lane, const float* g, uint32_t i) {
+    (void)lane;
+    __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)(g + i),
+                                     (__attribute__((address_space(3))) void*)lds_wave, 4, 0, 0);
+}
+#else
+inline void lds_copy_word(float* lds_wave, int lane, const float* g, uint32_t i) { lds_wave[lane] = g[i]; }
+#endif
+
+// Wait for the wave's vector-memory loads (vmcnt(0) on the GPU; nothing on the host).
+#if defined(__HIP_DEVICE_COMPILE__)
+__device__ __forceinline__ void vm_drain() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+#else
+inline void vm_drain() {}
+#endif
+
 // Bounds-checked (emulation) view of a global array.
 template <class T>
 struct GView {
@@ -303,6 +325,7 @@ struct Layout {
         EXW = NW * C::WL;
         SOREC = (int64_t)jmax * C::S * C::H * C::F;  // per PE side
         EXR = npts_max + 2 * C::S * C::H;
+        if (C::F32) EXR = (EXR + 63) & ~int64_t(63);   // whole wave-sized chunks (direct copy)
         const int64_t SR = C::S > 1 ? C::S - 1 : 1;
         int64_t o = 0;
         // the raw range is consumed before the main region is first written
@@ -361,12 +384,14 @@ AT_HD AT_FI uint64_t delay_prefix(const ProbDev& P, int64_t step) {
 }
 
 // delay of counter (idx, side) given the step's prefix
-AT_HD AT_FI int draw_delay(const ProbDev& P, uint64_t prefix, int64_t idx, int side) {
+// (kmax and n_cdf from the uniform copy of the descriptor; the thresholds cdf, indexed
+// at run time, from the descriptor in memory, read only for a non-uniform law)
+AT_HD AT_FI int draw_delay(const ProbDev& P, const uint64_t* cdf, uint64_t prefix, int64_t idx, int side) {
     const uint64_t z = mix64(prefix + GOLDEN * (uint64_t)(2 * idx + side + 1));
     const uint64_t top = z >> 32;
     if (P.n_cdf == 0) return (int)((top * (uint64_t)(P.kmax + 1)) >> 32);
     int k = 0;
-    while (k < P.kmax && top >= P.cdf[k]) ++k;
+    while (k < P.kmax && top >= cdf[k]) ++k;
     return k;
 }
 
@@ -928,12 +953,15 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const ProbDev& P_
             const int64_t oi = ((n - P.ov_step0) * P.p + pe) * 2 + side;
             AT_CHECK(oi >= 0 && oi < P.ov_n * P.p * 2, "override", oi, P.ov_n * P.p * 2);
             kd = gld(P.ov, (uint32_t)oi);
+            // consumed here, so that no later join of the paths waits for the vector-memory
+            // counter (which would also wait for the tile's direct copies in flight)
+            vm_drain();
         } else if (P.gran == G_PE) {
-            kd = draw_delay(P_in, dprefix, pe, 0);
+            kd = draw_delay(P, P_in.cdf, dprefix, pe, 0);
         } else if (P.gran == G_PE_SIDE) {
-            kd = draw_delay(P_in, dprefix, pe, side);
+            kd = draw_delay(P, P_in.cdf, dprefix, pe, side);
         } else {
-            kd = draw_delay(P_in, dprefix, side == 0 ? pe : (pe + 1 == P.p ? 0 : pe + 1), 0);
+            kd = draw_delay(P, P_in.cdf, dprefix, side == 0 ? pe : (pe + 1 == P.p ? 0 : pe + 1), 0);
         }
         int ke;
         if (P.mode == M_AT) {
@@ -955,9 +983,12 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const ProbDev& P_
     const double invP = 1.0 / (double)Pp;
     constexpr int nrec = S * H * F;              // lo (FP32) or value (FP64) words of a level
     constexpr int nhi = C::F32 ? H * F : 1;      // FP32 hi words of a level
-    // levels of the first PE side loaded before the raw range is stored (one in FP64,
-    // whose records take twice the registers)
-    constexpr int JPF = C::F32 ? 0 : 1;
+    // FP32 forms: the raw range is copied into LDS directly (no registers), and all
+    // levels of the first PE side are loaded before it is waited for; FP64: the raw
+    // range goes through registers, and one level (the records take twice the
+    // registers) is loaded before it is stored
+    constexpr bool RAW_DMA = C::F32;
+    constexpr int JPF = C::F32 ? (JM < 3 ? JM : 3) : 1;
     constexpr int JPR = JPF > 0 ? JPF : 1;
     // delays of a PE side (into LDS, and the log); the number of ring levels it reads
     auto side_delays = [&](int side_idx, int& ke) -> int {
@@ -1000,25 +1031,48 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const ProbDev& P_
         AT_CHECK(nraw <= nth * (PPT + 1), "raw range", nraw, nth * (PPT + 1));
         // loads of the raw range and of the first PE side's ring levels are all issued
         // before any of them is stored, so that their latencies overlap
-        LR vh[PPT + 1][F];
-        float vl[PPT + 1][F];
-        {
-            // the range wraps round the periodic domain only in a problem's first and last tile
-            const bool wraps = t.lo < SH || t.lo + t.npts + SH > N;
-            const int Ni = (int)N, xs = (int)t.lo - SH;
+        LR vh[RAW_DMA ? 1 : PPT + 1][F];
+        float vl[RAW_DMA ? 1 : PPT + 1][F];
+        // the range wraps round the periodic domain only in a problem's first and last tile
+        const bool wraps = t.lo < SH || t.lo + t.npts + SH > N;
+        const int Ni = (int)N, xs = (int)t.lo - SH;
+        auto raw_x = [&](int r) -> int {
+            int x = xs + r;
+            if (wraps) {
+                if (Ni >= SH) {
+                    x = x < 0 ? x + Ni : x;
+                    x = x >= Ni ? x - Ni : x;
+                } else {
+                    x = (int)wrapi(x, N);
+                }
+            }
+            return x;
+        };
+        if constexpr (RAW_DMA) {
+            // wave-sized chunks of 64 consecutive positions (the layout pads the range to
+            // a multiple of 64); lanes past the end of the range copy its last word
+            const int lane = tid & 63, wbase = tid & ~63;
+#pragma unroll
+            for (int k = 0; k <= PPT; ++k) {
+                const int r0 = wbase + k * nth;
+                if (r0 >= nraw) continue;
+                const int r = r0 + lane < nraw ? r0 + lane : nraw - 1;
+                const int x = raw_x(r);
+#pragma unroll
+                for (int f = 0; f < F; ++f) {
+                    const int64_t gi = f * N + x;
+                    AT_CHECK(gi >= 0 && gi < st.n, "raw copy", gi, st.n);
+                    lds_copy_word(&L.rh[f][r0], lane, st.p, (uint32_t)gi);
+                    if (use_lo) lds_copy_word(&L.rl[f][r0], lane, stlo.p, (uint32_t)gi);
+                    else L.rl[f][r0 + lane] = 0.f;
+                }
+            }
+        } else {
 #pragma unroll
             for (int k = 0; k <= PPT; ++k) {
                 const int r = tid + k * nth;
                 if (r >= nraw) continue;
-                int x = xs + r;
-                if (wraps) {
-                    if (Ni >= SH) {
-                        x = x < 0 ? x + Ni : x;
-                        x = x >= Ni ? x - Ni : x;
-                    } else {
-                        x = (int)wrapi(x, N);
-                    }
-                }
+                const int x = raw_x(r);
 #pragma unroll
                 for (int f = 0; f < F; ++f) {
                     vh[k][f] = st.ld(f * N + x);
@@ -1050,14 +1104,16 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const ProbDev& P_
             const int k = tid / JMAXW, l = tid % JMAXW;
             L.wt[tid] = l < JM ? WTAB.w[k == 0 ? 1 : J][k][l] : 0.0;
         }
+        if constexpr (!RAW_DMA) {
 #pragma unroll
-        for (int k = 0; k <= PPT; ++k) {
-            const int r = tid + k * nth;
-            if (r >= nraw) continue;
+            for (int k = 0; k <= PPT; ++k) {
+                const int r = tid + k * nth;
+                if (r >= nraw) continue;
 #pragma unroll
-            for (int f = 0; f < F; ++f) {
-                L.rh[f][r] = vh[k][f];
-                if constexpr (C::F32) L.rl[f][r] = vl[k][f];
+                for (int f = 0; f < F; ++f) {
+                    L.rh[f][r] = vh[k][f];
+                    if constexpr (C::F32) L.rl[f][r] = vl[k][f];
+                }
             }
         }
         if (has0) {
@@ -1105,7 +1161,9 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const ProbDev& P_
             }
         }
     });
-    rt.sync();
+    // the direct copies complete on the vector-memory counter: drained before the barrier
+    if constexpr (RAW_DMA) rt.sync_mem();
+    else rt.sync();
 
     // tile-local PE of own point i.  The PE owning global x = lo + i is ceil(z) - 1 with
     // z = (x + 1) P / N.  In FP32, z' = (i + 1) (P/N) + (lo P/N - pe0) is within 1e-4 of
