@@ -323,7 +323,10 @@ struct Layout {
         EXM = npts_max + 2 * C::H * (int64_t)npe_max;
         NW = npe_max + 1;
         EXW = NW * C::WL;
-        SOREC = (int64_t)jmax * C::S * C::H * C::F;  // per PE side
+        // per PE side: the delayed strips of jmax levels, or (FP32 scalar kind) their
+        // extrapolation to level n, one level's worth
+        const int64_t jl = C::HILO ? 1 : jmax;
+        SOREC = jl * C::S * C::H * C::F;
         EXR = npts_max + 2 * C::S * C::H;
         if (C::F32) EXR = (EXR + 63) & ~int64_t(63);   // whole wave-sized chunks (direct copy)
         const int64_t SR = C::S > 1 ? C::S - 1 : 1;
@@ -351,10 +354,10 @@ struct Layout {
         o_wq = o;    o += align16(2 * C::F * EXW * sl);
         o_wR = o;    o += rk_keeps_stage_rhs<C::S>() ? align16(SR * C::F * EXW * sl) : 0;
         o_SO = o;    o += align16(2 * (int64_t)npe_max * SOREC * sl);
-        o_SOhi = o;  o += C::F32 ? align16(2 * (int64_t)npe_max * jmax * C::H * C::F * 4) : 0;
+        o_SOhi = o;  o += C::F32 ? align16(2 * (int64_t)npe_max * jl * C::H * C::F * 4) : 0;
         o_pelo = o;  o += align16((npe_max + 1) * 4);
         o_keff = o;  o += align16(2 * (int64_t)npe_max * 4);
-        o_wt = o;    o += align16(16 * JMAXW * 8);      // extrapolation weights [k][l]
+        o_wt = o;    o += C::HILO ? 0 : align16(16 * JMAXW * 8);   // extrapolation weights [k][l]
         total = o;
     }
 };
@@ -540,7 +543,8 @@ struct Lds {
     View<L> wu[C::F], wq[2][C::F];
     View<float> wulo[C::F];
     View<L> wR[SR][C::F];
-    View<L> SO;                // delayed strips [side][level][stage][h][f] (FP32: lo parts)
+    View<L> SO;                // delayed strips [side][level][stage][h][f] (FP32: lo parts);
+                               // FP32 scalar kind: halo lo parts extrapolated to level n
     View<float> SOhi;          // FP32 forms: hi parts [side][level][h][f]
     View<int> pelo, keff;
     View<double> wt;           // extrapolation weights w_l(k) at [k * JMAXW + l]
@@ -548,6 +552,7 @@ struct Lds {
     View<float> rl[C::F];      // raw FP32 lo
     int EXM, EXW, SOREC, jmax;
     AT_HD void init(unsigned char* base, const Layout<C>& Lo, int npe_max, int jm) {
+        if (C::HILO) jm = 1;    // one extrapolated level per side
         EXM = (int)Lo.EXM; EXW = (int)Lo.EXW; SOREC = (int)Lo.SOREC; jmax = jm;
         const int64_t nm = Lo.EXM, nw = Lo.EXW;
         for (int par = 0; par < 2; ++par) {
@@ -589,7 +594,7 @@ struct Lds {
         SOhi = View<float>{(float*)(base + Lo.o_SOhi), C::F32 ? 2 * (int64_t)npe_max * jm * C::H * C::F : 0};
         pelo = View<int>{(int*)(base + Lo.o_pelo), npe_max + 1};
         keff = View<int>{(int*)(base + Lo.o_keff), 2 * (int64_t)npe_max};
-        wt = View<double>{(double*)(base + Lo.o_wt), 16 * JMAXW};
+        wt = View<double>{(double*)(base + Lo.o_wt), C::HILO ? 0 : 16 * JMAXW};
         for (int f = 0; f < C::F; ++f) {
             rh[f] = View<L>{(L*)(base + Lo.o_rh) + f * Lo.EXR, Lo.EXR};
             rl[f] = View<float>{(float*)(base + Lo.o_rl) + f * Lo.EXR, C::F32 ? Lo.EXR : 0};
@@ -1026,6 +1031,45 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const ProbDev& P_
             for (int r = 0; r < H * F; ++r) L.SOhi[(side_idx * L.jmax + l) * H * F + r] = vh[r];
         }
     };
+    // FP32 scalar kind: the halo of a PE side at every stage, extrapolated once per step
+    // (hi part: level 0's; lo part: level 0's plus the weighted differences of the other
+    // levels to it, in level order).  Levels below nreg are in registers (weights of
+    // levels 1.. in wl), the others are loaded here.
+    auto hq_put = [&](int side_idx, int ke, int jeff, int nreg, const LR (&rv)[JPR][nrec],
+                      const float (&rvh)[JPR][nhi], const float (&wl)[JPR]) {
+        float hi[nhi], lo[nrec];
+#pragma unroll
+        for (int r = 0; r < nhi; ++r) hi[r] = rvh[0][r];
+#pragma unroll
+        for (int r = 0; r < nrec; ++r) lo[r] = rv[0][r];
+#pragma unroll
+        for (int l = 1; l < JM; ++l) {
+            if (l >= jeff) continue;
+            LR v[nrec];
+            float vh[nhi];
+            float w;
+            if (l < JPR && l < nreg) {
+                const int lr = l < JPR ? l : 0;
+#pragma unroll
+                for (int r = 0; r < nrec; ++r) v[r] = rv[lr][r];
+#pragma unroll
+                for (int r = 0; r < nhi; ++r) vh[r] = rvh[lr][r];
+                w = wl[lr];
+            } else {
+                ring_ld(side_idx, ke, l, v, vh);
+                w = (float)WTAB.w[J][ke][l];
+            }
+#pragma unroll
+            for (int r = 0; r < nrec; ++r) {
+                const int hf = r % (H * F);       // record word r = (s H + h) F + f
+                lo[r] += w * ((vh[hf] - hi[hf]) + (v[r] - rv[0][r]));
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < nhi; ++r) L.SOhi[side_idx * H * F + r] = hi[r];
+#pragma unroll
+        for (int r = 0; r < nrec; ++r) L.SO[side_idx * L.SOREC + r] = lo[r];
+    };
     rt.each([&](int tid, TS<C>& ts) {
         const int nraw = t.npts + 2 * SH;
         AT_CHECK(nraw <= nth * (PPT + 1), "raw range", nraw, nth * (PPT + 1));
@@ -1084,12 +1128,18 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const ProbDev& P_
         const bool has0 = si0 < 2 * t.npe;
         LR rv[JPR][nrec];
         float rvh[JPR][nhi];
+        float wl[JPR];
         int jeff0 = 0, ke0 = 0;
         if (has0) {
             jeff0 = side_delays(si0, ke0);
 #pragma unroll
             for (int l = 0; l < JPF; ++l)
                 if (l < jeff0) ring_ld(si0, ke0, l, rv[l], rvh[l]);
+            if constexpr (C::HILO) {
+#pragma unroll
+                for (int l = 1; l < JPF; ++l)
+                    if (l < jeff0) wl[l] = (float)WTAB.w[J][ke0][l];
+            }
         }
         for (int k = first_item(tid, nth, 3); k <= t.npe; k += nth) {
             // floor(p N / P) of PE p = pe0 + k: estimated in double, then corrected exactly
@@ -1100,7 +1150,7 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const ProbDev& P_
             AT_CHECK(lo * Pp <= num && (lo + 1) * Pp > num, "PE offset", lo, num);
             L.pelo[k] = (int)(lo - t.lo);
         }
-        if (tid < 16 * JMAXW) {   // weights for delay k (J levels; k = 0 uses one level)
+        if (!C::HILO && tid < 16 * JMAXW) {   // weights for delay k (J levels; k = 0 uses one level)
             const int k = tid / JMAXW, l = tid % JMAXW;
             L.wt[tid] = l < JM ? WTAB.w[k == 0 ? 1 : J][k][l] : 0.0;
         }
@@ -1116,30 +1166,42 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const ProbDev& P_
                 }
             }
         }
-        if (has0) {
-#pragma unroll
-            for (int l = 0; l < JPF; ++l)
-                if (l < jeff0) ring_put(si0, l, rv[l], rvh[l]);
-#pragma unroll
-            for (int l = JPF; l < JM; ++l) {
-                if (l >= jeff0) continue;
-                LR v[nrec];
-                float vh[nhi];
-                ring_ld(si0, ke0, l, v, vh);
-                ring_put(si0, l, v, vh);
+        if constexpr (C::HILO) {
+            if (has0 && jeff0 > 0) hq_put(si0, ke0, jeff0, JPF, rv, rvh, wl);
+            // further PE sides (tiles of more than nth / 2 PEs)
+            for (int side_idx = si0 + nth; side_idx < 2 * t.npe; side_idx += nth) {
+                int ke;
+                const int jeff = side_delays(side_idx, ke);
+                if (jeff == 0) continue;
+                ring_ld(side_idx, ke, 0, rv[0], rvh[0]);
+                hq_put(side_idx, ke, jeff, 1, rv, rvh, wl);
             }
-        }
-        // further PE sides (tiles of more than nth / 2 PEs)
-        for (int side_idx = si0 + nth; side_idx < 2 * t.npe; side_idx += nth) {
-            int ke;
-            const int jeff = side_delays(side_idx, ke);
+        } else {
+            if (has0) {
 #pragma unroll
-            for (int l = 0; l < JM; ++l) {
-                if (l >= jeff) continue;
-                LR v[nrec];
-                float vh[nhi];
-                ring_ld(side_idx, ke, l, v, vh);
-                ring_put(side_idx, l, v, vh);
+                for (int l = 0; l < JPF; ++l)
+                    if (l < jeff0) ring_put(si0, l, rv[l], rvh[l]);
+#pragma unroll
+                for (int l = JPF; l < JM; ++l) {
+                    if (l >= jeff0) continue;
+                    LR v[nrec];
+                    float vh[nhi];
+                    ring_ld(si0, ke0, l, v, vh);
+                    ring_put(si0, l, v, vh);
+                }
+            }
+            // further PE sides (tiles of more than nth / 2 PEs)
+            for (int side_idx = si0 + nth; side_idx < 2 * t.npe; side_idx += nth) {
+                int ke;
+                const int jeff = side_delays(side_idx, ke);
+#pragma unroll
+                for (int l = 0; l < JM; ++l) {
+                    if (l >= jeff) continue;
+                    LR v[nrec];
+                    float vh[nhi];
+                    ring_ld(side_idx, ke, l, v, vh);
+                    ring_put(side_idx, l, v, vh);
+                }
             }
         }
         if (stage_io) {
@@ -1236,27 +1298,18 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const ProbDev& P_
         constexpr int s = decltype(sc)::value;
         const QV<C>& M = L.main[s & 1];
         const int e = halo_e(side_idx >> 1, side_idx & 1, h);
-        const int ke = L.keff[side_idx];
-        const int jeff = ke == 0 ? 1 : J;
-        double w[JM];
-#pragma unroll
-        for (int l = 0; l < JM; ++l) w[l] = L.wt[ke * JMAXW + l];
         const int sob = side_idx * L.SOREC;
-        const int sohb = side_idx * L.jmax;
         if constexpr (C::HILO) {
-            const float h0 = L.SOhi[((sohb + 0) * H + h) * F];
-            const float l0 = L.SO[sob + ((0 * S + s) * H + h) * F];
-            float lo = l0;
-#pragma unroll
-            for (int l = 1; l < JM; ++l) {
-                if (l >= jeff) continue;
-                const float hl = L.SOhi[((sohb + l) * H + h) * F];
-                const float ll = L.SO[sob + ((l * S + s) * H + h) * F];
-                lo += float(w[l]) * ((hl - h0) + (ll - l0));
-            }
-            if (s == s0) M.g[0][e] = h0;
-            M.glo[e] = lo;
+            // extrapolated in the load phase
+            if (s == s0) M.g[0][e] = L.SOhi[side_idx * H * F + h * F];
+            M.glo[e] = L.SO[sob + (s * H + h) * F];
         } else {
+            const int ke = L.keff[side_idx];
+            const int jeff = ke == 0 ? 1 : J;
+            double w[JM];
+#pragma unroll
+            for (int l = 0; l < JM; ++l) w[l] = L.wt[ke * JMAXW + l];
+            const int sohb = side_idx * L.jmax;
             Q gl[NQ], g0[NQ], acc[NQ];
             Q lam0 = Q(0), laml = Q(0);
 #pragma unroll
