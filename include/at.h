@@ -107,11 +107,12 @@ typedef struct at_problem_desc {
  *   override_steps  capacity, in steps, of the delay-override buffer (0 = off).
  *   stage_api       1 = reserve the stage buffers that at_rk_stage needs.
  *   lds_budget      bytes of LDS per tile the planner packs PEs up to (0 = the
- *                   default of the kernel: 28 KiB, 5 workgroups per compute unit,
- *                   for the FP32 scalar finite-difference kernels, whose registers
- *                   allow 5 waves per SIMD; 40 KiB, 4 workgroups, otherwise); a
- *                   tile of one PE may exceed it (up to the 160 KiB of a compute
- *                   unit).
+ *                   default of the kernel: 26 KiB, 6 workgroups per compute unit,
+ *                   for the FP32 scalar finite-difference kernels of order 2 and 4,
+ *                   whose whole-step kernel is held to the registers of 6 waves per
+ *                   SIMD; 40 KiB, 4
+ *                   workgroups, otherwise); a tile of one PE may exceed it (up to
+ *                   the 160 KiB of a compute unit).
  */
 typedef struct at_run_opts {
     int32_t tile_points, persistent, grid_per_cu, graph_steps;

@@ -47,7 +47,7 @@ __device__ __forceinline__ int xcd_item(int it, int n) {
 }
 
 template <class C, bool STEP>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(C::WAVES_PER_EU)))
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(STEP ? C::WAVES_STEP : C::WAVES_PER_EU)))
 void at_tile_kernel(KArgs a) {
     extern __shared__ __align__(16) unsigned char lds[];
     GpuRT<C> rt;

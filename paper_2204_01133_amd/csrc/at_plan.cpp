@@ -186,10 +186,12 @@ int make_plan(const at_problem_desc* probs, int n_probs, const at_run_opts* opts
         const at_problem_desc& d = plan.desc[b];
         ProbInfo& pi = plan.info[b];
         VariantKey ks = pi.key, kl = pi.key;
-        // default LDS per tile: 5 workgroups per compute unit for the FP32 scalar FD
-        // kernels (few enough registers for 5 waves per SIMD), 4 for the others
+        // default LDS per tile: 6 workgroups per compute unit for the FP32 scalar FD
+        // kernels of halo width up to 2 (whose whole-step kernel is held to 6 waves per
+        // SIMD), 4 for the others
         const int64_t lds_budget = plan.opts.lds_budget > 0 ? plan.opts.lds_budget
-                                   : (pi.key.kind == K_ADR && pi.key.f32) ? 28 * 1024 : 40 * 1024;
+                                   : (pi.key.kind == K_ADR && pi.key.f32 && pi.key.H <= 2) ? 26 * 1024
+                                                                                          : 40 * 1024;
         kl.ppt = ppt_large(pi.key.kind, pi.key.f32);
         const int tsmall = BLOCK * ks.ppt, tlarge = BLOCK * kl.ppt;
         const int target = plan.opts.tile_points > 0 ? std::min(plan.opts.tile_points, tsmall) : tsmall;

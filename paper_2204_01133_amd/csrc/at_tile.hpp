@@ -299,6 +299,10 @@ struct Cfg {
     // small-tile scalar FD kernels (8 points per thread in FP32, 6 in FP64) are held to
     // 128 VGPRs (4 waves) instead of ~160 (3)
     static constexpr int WAVES_PER_EU = (KIND_ == K_ADR && PPT_ == (F32_ ? 8 : 6)) ? 4 : 1;
+    // the whole-step FP32 scalar FD kernel of halo width up to 2 is held to 80 VGPRs
+    // (6 waves), which its default LDS per tile (26 KiB, 6 workgroups per compute unit)
+    // matches
+    static constexpr int WAVES_STEP = (KIND_ == K_ADR && F32_ && PPT_ == 8 && H_ <= 2) ? 6 : WAVES_PER_EU;
 };
 
 AT_HD AT_FI int64_t align16(int64_t b) { return (b + 15) & ~int64_t(15); }
