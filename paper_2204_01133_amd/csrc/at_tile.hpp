@@ -762,29 +762,36 @@ AT_HD AT_FI void iface_flux(const QV<C>& L, const PhysP& P, int64_t e) {
 }
 
 // K at ext position e; q = the point's own state (qreal) for sources / primitives
+// FP32 scalar FD kind: -c u_x + alpha u_xx (+ r u (1 - u)) at ext position e whose own
+// hi and lo values hc, lc the caller holds (they equal the region's values at e), as
+// one central stencil on differences to the centre (the weights of each derivative sum
+// to zero), hi and lo differences taken separately (hi - hi exact for neighbouring values)
+template <class C>
+AT_HD AT_FI float rhs_adr_hilo(const QV<C>& L, const PhysP& P, int64_t e, float hc, float lc) {
+    float k = 0.f;
+#pragma unroll
+    for (int o = 1; o <= C::H; ++o) {
+        const float dp = (L.g[0][e + o] - hc) + (L.glo[e + o] - lc);
+        const float dm = (L.g[0][e - o] - hc) + (L.glo[e - o] - lc);
+        k += P.lpf[o - 1] * dp;
+        k += P.lmf[o - 1] * dm;
+    }
+    if (P.pde == PDE_ADR_LOGISTIC) {
+        const float u = hc + lc;
+        k += P.rf * u * (1.f - u);
+    }
+    return k;
+}
+
 template <class C>
 AT_HD AT_FI void rhs_at(const QV<C>& L, const PhysP& P, int64_t e, const typename C::qreal* q,
                         typename C::lreal* K) {
     using LR = typename C::lreal;
     if constexpr (C::KIND == K_ADR) {
         // -c u_x + alpha u_xx as one central stencil on differences to the centre
-        // (the weights of each derivative sum to zero); FP32 forms: hi and lo
-        // differences taken separately (hi - hi exact for neighbouring values)
+        // (the weights of each derivative sum to zero)
         if constexpr (C::HILO) {
-            const float hc = L.g[0][e], lc = L.glo[e];
-            float k = 0.f;
-#pragma unroll
-            for (int o = 1; o <= C::H; ++o) {
-                const float dp = (L.g[0][e + o] - hc) + (L.glo[e + o] - lc);
-                const float dm = (L.g[0][e - o] - hc) + (L.glo[e - o] - lc);
-                k += P.lpf[o - 1] * dp;
-                k += P.lmf[o - 1] * dm;
-            }
-            if (P.pde == PDE_ADR_LOGISTIC) {
-                const float u = hc + lc;
-                k += P.rf * u * (1.f - u);
-            }
-            K[0] = k;
+            K[0] = rhs_adr_hilo<C>(L, P, e, L.g[0][e], L.glo[e]);
         } else {
             const LR uc = L.g[0][e];
             LR k = LR(0);
@@ -1479,7 +1486,10 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const ProbDev& P_
 #pragma unroll
                     for (int f = 0; f < F; ++f) q[f] = own_state(ts, k, f, sc, vlo);
                     LR K[F];
-                    rhs_at<C>(Mc, PP, e, q, K);
+                    // the centre's hi part from registers, its lo part from LDS (holding the
+                    // recomputed lo live as well costs registers)
+                    if constexpr (C::HILO) K[0] = rhs_adr_hilo<C>(Mc, PP, e, ts.uh[k][0], Mc.glo[e]);
+                    else rhs_at<C>(Mc, PP, e, q, K);
 #pragma unroll
                     for (int f = 0; f < F; ++f) {
                         ts.K[s][k][f] = K[f];
@@ -1510,13 +1520,20 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const ProbDev& P_
                     const int b = idx / nr, w = rlo + (idx - b * nr);
                     const int wp = b * WL + w;
                     Q q[F];
+                    float whi = 0.f, wlo = 0.f;
 #pragma unroll
                     for (int f = 0; f < F; ++f) {
-                        if constexpr (C::F32) q[f] = (Q)L.wu[f][wp] + (Q)L.wq[s & 1][f][wp];
-                        else q[f] = (Q)L.wq[s & 1][f][wp];
+                        if constexpr (C::F32) {
+                            whi = L.wu[f][wp];
+                            wlo = L.wq[s & 1][f][wp];
+                            q[f] = (Q)whi + (Q)wlo;
+                        } else {
+                            q[f] = (Q)L.wq[s & 1][f][wp];
+                        }
                     }
                     LR K[F];
-                    rhs_at<C>(Wc, PP, wp, q, K);
+                    if constexpr (C::HILO) K[0] = rhs_adr_hilo<C>(Wc, PP, wp, whi, wlo);
+                    else rhs_at<C>(Wc, PP, wp, q, K);
                     Q qn[F];
                     LR hv[F];
                     float lvn[F];
