@@ -1393,12 +1393,8 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const ProbDev& P_
                     }
                     strip_out(b, w, 0, f, C::F32 ? (LR)lv[f] : hv[f], (float)hv[f]);
                 }
-                if constexpr (C::HILO) {
-                    L.win[0].g[0][wp] = hv[0];
-                    L.win[0].glo[wp] = lv[0];
-                } else {
-                    put_quant<C>(L.win[0], PP, wp, q);
-                }
+                // FP32 scalar kind: the window's quantities are the state just written
+                if constexpr (!C::HILO) put_quant<C>(L.win[0], PP, wp, q);
             }
         }
     });
@@ -1566,12 +1562,9 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const ProbDev& P_
                             strip_out(b, w, s + 1, f, v, 0.f);
                         }
                     }
-                    if constexpr (C::HILO) {
-                        Wn.g[0][wp] = hv[0];
-                        Wn.glo[wp] = lvn[0];
-                    } else {
-                        put_quant<C>(Wn, PP, wp, qn);
-                    }
+                    // FP32 scalar kind: the window's quantities are its state (hi in wu, lo in
+                    // the stage parity's wq, written above), nothing more to write
+                    if constexpr (!C::HILO) put_quant<C>(Wn, PP, wp, qn);
                     // a halo point of a PE side with delay 0: its stage s+1 quantities
                     const int h2 = w - (S - 1) * H;
                     if (next_active && h2 >= 0 && h2 < 2 * H) {
