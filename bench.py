@@ -222,7 +222,7 @@ def main():
             "bytes_per_launch": bytes32["total"],
             "avg_launch_us": t32 / K * 1e6,
             "launches_per_step": launches,
-            "kernel": "at_tile_kernel<Cfg<0, 2, 4, true, 8>> (scalar FD, H=2, RK4, FP32C, 8 points/thread)",
+            "kernel": "at_tile_kernel<Cfg<0, 2, 4, true, 8>, true> (scalar FD, H=2, RK4, FP32C, 8 points/thread, whole-step form)",
         },
         "cpu_baseline": None if cpu_rate is None else {
             "value": cpu_rate,
