@@ -46,17 +46,27 @@ __device__ __forceinline__ int xcd_item(int it, int n) {
     return x * q + (x < r ? x : r) + j;
 }
 
+// The tile list, the problem descriptors and the step counter are not written while a
+// tile kernel runs: they are read through the constant address space, so that their
+// uniform reads are scalar loads (one request per cache line, no per-lane loads and
+// register moves) also inside the tile loop, where the compiler could not otherwise
+// rule out an aliasing store.
+template <class T>
+__device__ __forceinline__ const AT_CONST T& const_ref(const T* p) {
+    return *(const AT_CONST T*)p;
+}
+
 template <class C, bool STEP>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(STEP ? C::WAVES_STEP : C::WAVES_PER_EU)))
 void at_tile_kernel(KArgs a) {
     extern __shared__ __align__(16) unsigned char lds[];
     GpuRT<C> rt;
-    const int64_t n = (a.step_ptr ? *a.step_ptr : 0) + a.step_off;
+    const int64_t n = (a.step_ptr ? const_ref(a.step_ptr) : 0) + a.step_off;
     const bool remap = (a.flags & KF_XCD) && (int)gridDim.x == a.ntiles;
     for (int it = blockIdx.x; it < a.ntiles; it += gridDim.x) {
         const int ti = remap ? xcd_item(it, a.ntiles) : it;
-        const Tile t = a.tiles[ti];
-        tile_step<C, STEP>(rt, a, t, a.tprobs[ti], n, lds);
+        const Tile t = const_ref(a.tiles + ti);
+        tile_step<C, STEP>(rt, a, t, const_ref(a.tprobs + ti), n, lds);
         if (it + (int)gridDim.x < a.ntiles) rt.sync();   // LDS reused by the next tile
     }
 }

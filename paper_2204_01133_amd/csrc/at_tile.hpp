@@ -36,6 +36,15 @@
 #define AT_FI inline
 #endif
 
+// Memory that no kernel writes while it runs (problem descriptors, the tile list): on
+// the GPU it is read through the constant address space, so that uniform reads of it
+// are scalar loads.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define AT_CONST __attribute__((address_space(4)))
+#else
+#define AT_CONST
+#endif
+
 #ifdef AT_EMU
 void at_emu_fail(const char* what, const char* file, int line, long long i, long long n);
 #define AT_CHECK(c, what, i, n) \
@@ -199,7 +208,7 @@ AT_HD AT_FI T* uni_ptr(T* p) { return (T*)(uintptr_t)uni((int64_t)(uintptr_t)p);
 // tile, so no later access goes back to memory.  Its arrays are only ever indexed with
 // compile-time indices (a run-time index would put the copy in scratch memory), so the
 // delay thresholds cdf, which the delay draw indexes at run time, are not copied.
-AT_HD AT_FI ProbDev uniform_copy(const ProbDev& P) {
+AT_HD AT_FI ProbDev uniform_copy(const AT_CONST ProbDev& P) {
     ProbDev u;
     u.n = uni(P.n);
     u.p = uni(P.p); u.pde = uni(P.pde); u.mode = uni(P.mode); u.gran = uni(P.gran);
@@ -393,7 +402,7 @@ AT_HD AT_FI uint64_t delay_prefix(const ProbDev& P, int64_t step) {
 // delay of counter (idx, side) given the step's prefix
 // (kmax and n_cdf from the uniform copy of the descriptor; the thresholds cdf, indexed
 // at run time, from the descriptor in memory, read only for a non-uniform law)
-AT_HD AT_FI int draw_delay(const ProbDev& P, const uint64_t* cdf, uint64_t prefix, int64_t idx, int side) {
+AT_HD AT_FI int draw_delay(const ProbDev& P, const AT_CONST uint64_t* cdf, uint64_t prefix, int64_t idx, int side) {
     const uint64_t z = mix64(prefix + GOLDEN * (uint64_t)(2 * idx + side + 1));
     const uint64_t top = z >> 32;
     if (P.n_cdf == 0) return (int)((top * (uint64_t)(P.kmax + 1)) >> 32);
@@ -860,7 +869,7 @@ AT_HD AT_FI int64_t ring_lo_off(int s, int h, int f) { return (int64_t)C::H * C:
 // STEP: the launch is a whole step (stages 0..S-1, no stage inputs or outputs), so the
 // stage range is known at compile time; otherwise it is read from the arguments.
 template <class C, bool STEP, class RT>
-AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const ProbDev& P_in, int64_t n_in,
+AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const AT_CONST ProbDev& P_in, int64_t n_in,
                      unsigned char* lds_base) {
     const ProbDev P = uniform_copy(P_in);
     using LR = typename C::lreal;
