@@ -83,13 +83,20 @@ struct View {
 // uniform base the address is the scalar base plus a 32-bit vector offset (one VGPR,
 // not a 64-bit address pair per access).
 #if defined(__HIP_DEVICE_COMPILE__)
+// byte offset of element i in 32 bits (every array is under 4 GiB), added to the base as
+// an unsigned 32-bit value: the scalar-base + 32-bit vector-offset form of the access
+template <class T>
+__device__ __forceinline__ const __attribute__((address_space(1))) T* gptr(const T* p, uint32_t i) {
+    return (const __attribute__((address_space(1))) T*)((const __attribute__((address_space(1))) char*)p +
+                                                        (uint32_t)(i * (uint32_t)sizeof(T)));
+}
 template <class T>
 __device__ __forceinline__ T gld(const T* p, uint32_t i) {
-    return ((const __attribute__((address_space(1))) T*)p)[i];
+    return *gptr(p, i);
 }
 template <class T>
 __device__ __forceinline__ void gst(T* p, uint32_t i, T v) {
-    ((__attribute__((address_space(1))) T*)p)[i] = v;
+    *(__attribute__((address_space(1))) T*)gptr((const T*)p, i) = v;
 }
 #else
 template <class T>
@@ -106,7 +113,7 @@ inline void gst(T* p, uint32_t i, T v) { p[i] = v; }
 #if defined(__HIP_DEVICE_COMPILE__)
 __device__ __forceinline__ void lds_copy_word(float* lds_wave, int lane, const float* g, uint32_t i) {
     (void)lane;
-    __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)(g + i),
+    __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)gptr(g, i),
                                      (__attribute__((address_space(3))) void*)lds_wave, 4, 0, 0);
 }
 #else
