@@ -1039,14 +1039,32 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const AT_CONST Pr
     };
     auto ring_ld = [&](int side_idx, int ke, int l, LR (&v)[nrec], float (&vh)[nhi]) {
         const uint32_t w0 = rec_back(ke + l, side_idx >> 1, side_idx & 1);
+        if constexpr (C::F32 && (H * F + nrec) % 2 == 0) {
+            // an even number of words: every record is 8-byte aligned (the ring base is
+            // 256-byte aligned), so the record is read as 64-bit words
+            constexpr int nw = H * F + nrec;
 #pragma unroll
-        for (int r = 0; r < nrec; ++r) {
-            if constexpr (C::F32) v[r] = gld(ring_f, w0 + (uint32_t)(H * F + r));
-            else v[r] = gld((const double*)ring_f, w0 / 2 + (uint32_t)r);
-        }
-        if constexpr (C::F32) {
+            for (int j = 0; j < nw / 2; ++j) {
+                const uint64_t d = gld((const uint64_t*)ring_f, w0 / 2 + (uint32_t)j);
+                const float w[2] = {__builtin_bit_cast(float, (uint32_t)d),
+                                    __builtin_bit_cast(float, (uint32_t)(d >> 32))};
 #pragma unroll
-            for (int r = 0; r < H * F; ++r) vh[r] = gld(ring_f, w0 + (uint32_t)r);
+                for (int u = 0; u < 2; ++u) {
+                    const int r = 2 * j + u;
+                    if (r < H * F) vh[r < H * F ? r : 0] = w[u];
+                    else v[r >= H * F ? r - H * F : 0] = w[u];
+                }
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < nrec; ++r) {
+                if constexpr (C::F32) v[r] = gld(ring_f, w0 + (uint32_t)(H * F + r));
+                else v[r] = gld((const double*)ring_f, w0 / 2 + (uint32_t)r);
+            }
+            if constexpr (C::F32) {
+#pragma unroll
+                for (int r = 0; r < H * F; ++r) vh[r] = gld(ring_f, w0 + (uint32_t)r);
+            }
         }
     };
     auto ring_put = [&](int side_idx, int l, const LR (&v)[nrec], const float (&vh)[nhi]) {
