@@ -343,11 +343,14 @@ struct Layout {
         EXM = npts_max + 2 * C::H * (int64_t)npe_max;
         NW = npe_max + 1;
         EXW = NW * C::WL;
+        if (C::HILO) EXW = (EXW + 63) & ~int64_t(63);   // whole wave-sized chunks (direct copy)
         // per PE side: the delayed strips of jmax levels, or (FP32 scalar kind) their
         // extrapolation to level n, one level's worth
         const int64_t jl = C::HILO ? 1 : jmax;
         SOREC = jl * C::S * C::H * C::F;
-        EXR = npts_max + 2 * C::S * C::H;
+        // FP32 scalar kind: no raw range (own points go to registers, windows straight
+        // into the window region)
+        EXR = C::HILO ? 0 : npts_max + 2 * C::S * C::H;
         if (C::F32) EXR = (EXR + 63) & ~int64_t(63);   // whole wave-sized chunks (direct copy)
         const int64_t SR = C::S > 1 ? C::S - 1 : 1;
         int64_t o = 0;
@@ -560,6 +563,7 @@ struct Lds {
     using L = typename C::lreal;
     static constexpr int SR = C::S > 1 ? C::S - 1 : 1;
     QV<C> main[2], win[2];     // main: stage parities
+    QV<C> win0;                // FP32 scalar kind: stage-0 window view (lo in wulo)
     View<L> wu[C::F], wq[2][C::F];
     View<float> wulo[C::F];
     View<L> wR[SR][C::F];
@@ -609,6 +613,9 @@ struct Lds {
                     win[par].g[0] = wq[par][0];
                 }
             }
+            // stage 0 of a window is u^n itself: hi in wu, lo in wulo
+            win0 = win[0];
+            if constexpr (C::HILO) win0.glo = wulo[0];
         }
         SO = View<L>{(L*)(base + Lo.o_SO), 2 * (int64_t)npe_max * Lo.SOREC};
         SOhi = View<float>{(float*)(base + Lo.o_SOhi), C::F32 ? 2 * (int64_t)npe_max * jm * C::H * C::F : 0};
@@ -1013,6 +1020,15 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const AT_CONST Pr
     //   PE offsets, delays, delayed strips of the ring, stage inputs (per-stage mode)
     constexpr int SH = S * H;
     const double invP = 1.0 / (double)Pp;
+    // floor(p N / P), the first point of PE p: estimated in double, then corrected exactly
+    auto pe_offset = [&](int64_t pe) -> int64_t {
+        const int64_t num = pe * N;
+        int64_t lo = (int64_t)((double)num * invP);
+        if (lo * Pp > num) --lo;
+        else if ((lo + 1) * Pp <= num) ++lo;
+        AT_CHECK(lo * Pp <= num && (lo + 1) * Pp > num, "PE offset", lo, num);
+        return lo;
+    };
     constexpr int nrec = S * H * F;              // lo (FP32) or value (FP64) words of a level
     constexpr int nhi = C::F32 ? H * F : 1;      // FP32 hi words of a level
     // FP32 forms: the raw range is copied into LDS directly (no registers), and all
@@ -1020,6 +1036,10 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const AT_CONST Pr
     // range goes through registers, and one level (the records take twice the
     // registers) is loaded before it is stored
     constexpr bool RAW_DMA = C::F32;
+    // FP32 scalar kind: no raw range; own points are loaded into registers and the
+    // boundary windows copied straight into the window region, so that the own-point
+    // and window set-up needs no phase (and barrier) of its own
+    constexpr bool OWN_REG = C::HILO;
     constexpr int JPF = C::F32 ? (JM < 3 ? JM : 3) : 1;
     constexpr int JPR = JPF > 0 ? JPF : 1;
     // delays of a PE side (into LDS, and the log); the number of ring levels it reads
@@ -1137,7 +1157,33 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const AT_CONST Pr
             }
             return x;
         };
-        if constexpr (RAW_DMA) {
+        if constexpr (OWN_REG) {
+            // own points into registers (inside [0, N): no wrap)
+#pragma unroll
+            for (int k = 0; k < PPT; ++k) {
+                const int i = tid + k * nth;
+                if (i >= t.npts) continue;
+                const int64_t x = t.lo + i;
+                ts.uh[k][0] = st.ld(x);
+                ts.ul[k][0] = use_lo ? stlo.ld(x) : 0.f;
+            }
+            // the boundary windows of level n, straight into the window region: wave-sized
+            // chunks of 64 consecutive window positions (the layout pads the region to a
+            // multiple of 64); lanes past the last position copy its word
+            if (first) {
+                const int nwin = (t.npe + 1) * WL;
+                const int lane = tid & 63;
+                for (int c = tid & ~63; c < nwin; c += nth) {
+                    const int wp = c + lane < nwin ? c + lane : nwin - 1;
+                    const int b = wp / WL, w = wp - b * WL;
+                    const int x = raw_x((int)(pe_offset(t.pe0 + b) - t.lo) + w);
+                    AT_CHECK(x >= 0 && x < st.n, "window copy", x, st.n);
+                    lds_copy_word(&L.wu[0][c], lane, st.p, (uint32_t)x);
+                    if (use_lo) lds_copy_word(&L.wulo[0][c], lane, stlo.p, (uint32_t)x);
+                    else L.wulo[0][c + lane] = 0.f;
+                }
+            }
+        } else if constexpr (RAW_DMA) {
             // wave-sized chunks of 64 consecutive positions (the layout pads the range to
             // a multiple of 64); lanes past the end of the range copy its last word
             const int lane = tid & 63, wbase = tid & ~63;
@@ -1186,15 +1232,8 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const AT_CONST Pr
                     if (l < jeff0) wl[l] = (float)WTAB.w[J][ke0][l];
             }
         }
-        for (int k = first_item(tid, nth, 3); k <= t.npe; k += nth) {
-            // floor(p N / P) of PE p = pe0 + k: estimated in double, then corrected exactly
-            const int64_t num = (int64_t)(t.pe0 + k) * N;
-            int64_t lo = (int64_t)((double)num * invP);
-            if (lo * Pp > num) --lo;
-            else if ((lo + 1) * Pp <= num) ++lo;
-            AT_CHECK(lo * Pp <= num && (lo + 1) * Pp > num, "PE offset", lo, num);
-            L.pelo[k] = (int)(lo - t.lo);
-        }
+        for (int k = first_item(tid, nth, 3); k <= t.npe; k += nth)
+            L.pelo[k] = (int)(pe_offset(t.pe0 + k) - t.lo);
         if (!C::HILO && tid < 16 * JMAXW) {   // weights for delay k (J levels; k = 0 uses one level)
             const int k = tid / JMAXW, l = tid % JMAXW;
             L.wt[tid] = l < JM ? WTAB.w[k == 0 ? 1 : J][k][l] : 0.0;
@@ -1398,13 +1437,23 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const AT_CONST Pr
             if (i >= t.npts) continue;
             const int lo = pe_local(i);
             ts.e[k] = i + 2 * H * lo + H;
+            if constexpr (!OWN_REG) {
 #pragma unroll
-            for (int f = 0; f < F; ++f) {
-                ts.uh[k][f] = L.rh[f][i + SH];
-                ts.ul[k][f] = C::F32 ? L.rl[f][i + SH] : 0.f;
+                for (int f = 0; f < F; ++f) {
+                    ts.uh[k][f] = L.rh[f][i + SH];
+                    ts.ul[k][f] = C::F32 ? L.rl[f][i + SH] : 0.f;
+                }
             }
         }
-        if (first) {
+        if (OWN_REG && first) {
+            // the windows are in place: stage-0 records of level n of the halo positions
+            for (int idx = first_item(tid, nth, 0); idx < (t.npe + 1) * 2 * H; idx += nth) {
+                const int b = idx / (2 * H), w = (S - 1) * H + (idx - b * 2 * H);
+                const int wp = b * WL + w;
+                strip_out(b, w, 0, 0, L.wulo[0][wp], L.wu[0][wp]);
+            }
+        }
+        if (!OWN_REG && first) {
             for (int idx = first_item(tid, nth, 0); idx < (t.npe + 1) * WL; idx += nth) {
                 const int b = idx / WL, w = idx - b * WL;
                 const int r = L.pelo[b] + w;       // raw index of window position w
@@ -1432,7 +1481,9 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const AT_CONST Pr
             }
         }
     });
-    rt.sync();
+    // with own points in registers and the windows in place, the first stage's
+    // quantities below read nothing this phase wrote
+    if constexpr (!OWN_REG) rt.sync();
 
     // ---- A0: quantities of the first stage at own and halo points --------------------
     static_for<0, S>([&](auto sc) {
@@ -1449,10 +1500,11 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const AT_CONST Pr
                     const int wp = (k + side) * WL + (S - 1) * H + side * H + h;
                     const int e = halo_e(k, side, h);
                     const QV<C>& M = L.main[0];
+                    const QV<C>& W0 = C::HILO ? L.win0 : L.win[0];
 #pragma unroll
-                    for (int j = 0; j < NQ; ++j) M.g[j][e] = L.win[0].g[j][wp];
-                    if constexpr (C::HILO) M.glo[e] = L.win[0].glo[wp];
-                    if constexpr (C::WENO) M.lam[e] = L.win[0].lam[wp];
+                    for (int j = 0; j < NQ; ++j) M.g[j][e] = W0.g[j][wp];
+                    if constexpr (C::HILO) M.glo[e] = W0.glo[wp];
+                    if constexpr (C::WENO) M.lam[e] = W0.lam[wp];
                 } else {
                     halo_from_so(side_idx, h, sc);
                 }
@@ -1474,7 +1526,7 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const AT_CONST Pr
         if (!own_active && !win_active) return;
         const QV<C>& Mc = L.main[s & 1];
         const QV<C>& Mn = L.main[sn & 1];
-        const QV<C>& Wc = L.win[s & 1];
+        const QV<C>& Wc = (C::HILO && s == 0) ? L.win0 : L.win[s & 1];   // stage 0: u^n
         const QV<C>& Wn = L.win[(s + 1) & 1];
 
         // B1 (WENO): interface fluxes
@@ -1555,7 +1607,7 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const AT_CONST Pr
                     for (int f = 0; f < F; ++f) {
                         if constexpr (C::F32) {
                             whi = L.wu[f][wp];
-                            wlo = L.wq[s & 1][f][wp];
+                            wlo = (C::HILO && s == 0) ? L.wulo[f][wp] : L.wq[s & 1][f][wp];
                             q[f] = (Q)whi + (Q)wlo;
                         } else {
                             q[f] = (Q)L.wq[s & 1][f][wp];
