@@ -13,6 +13,7 @@ it: FP64 batched and FP64 plain (one launch per problem) on the same data,
 with the error of each against the FP64 oracle on sampled problems.
 
     python bench.py [--gpus 1] [--steps 1000] [--warmup 20]
+    python bench.py --config {c1,c2,c4,c5,c5batch} --steps 100   # other configurations, timing only
 """
 from __future__ import annotations
 
@@ -64,6 +65,12 @@ def algorithmic_bytes_per_step(prs, solver) -> dict:
             "total": state + strip_w + strip_r}
 
 
+def warmup_steps(warmup, steps, graph_steps=50):
+    """Untimed steps before the timed ones: at least one graph's worth when the timed
+    steps replay a graph, so that capturing and instantiating it is not timed."""
+    return max(warmup, graph_steps) if 0 < graph_steps <= steps else warmup
+
+
 def time_form(prs, steps, warmup, method="batch_step", graph_steps=50, **opts):
     import torch
     from paper_2204_01133_amd import ATSolver
@@ -71,7 +78,7 @@ def time_form(prs, steps, warmup, method="batch_step", graph_steps=50, **opts):
     with torch.cuda.stream(st):
         s = ATSolver(prs, stream=st, graph_steps=graph_steps, **opts)
         run = getattr(s, method)
-        run(warmup)
+        run(warmup_steps(warmup, steps, graph_steps) if method == "batch_step" else warmup)
         torch.cuda.synchronize()
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
@@ -113,15 +120,51 @@ def norm_err(got, ref):
     return float(np.abs(got - ref).max() / np.abs(ref).max())
 
 
+# the other configurations (parity cases of the tests): timed here for the record, not
+# bench lines of the headline metric
+OTHER_CONFIGS = {
+    "c1": ("advection-diffusion, N 1024, P 8, kmax 3, FD4 + AT, RK4", lambda: [W.adv_diff_c1()]),
+    "c2": ("reactive NS flame, N 8192, P 64, kmax 4, FD8 + AT (J 5), RK4", lambda: [W.reactive_ns_c2()]),
+    "c4": ("Euler Sod, N 65536, P 256, kmax 4, AT-WENO5 (J 2), SSP-RK3", lambda: [W.euler_sod_c4()]),
+    "c5": ("reactive Euler detonation, N 2^20, P 4096, kmax 4, AT-WENO5, SSP-RK3",
+           lambda: [W.detonation_c5()]),
+    "c5batch": ("256 detonation tubes, N uniform [16384, 131072], AT-WENO5, SSP-RK3",
+                lambda: W.detonation_batch_c5()),
+}
+
+
+def run_other(name, steps, warmup):
+    desc, make = OTHER_CONFIGS[name]
+    base = make()
+    pts = W.total_points(base)
+    stages = {"rk4": 4, "ssprk3": 3, "rk2": 2, "fe": 1}[base[0].rk]
+    forms = {}
+    warmup = warmup_steps(warmup, steps)
+    for prec in ("fp32c", "fp64"):
+        prs = [p.replace(precision=prec) for p in base]
+        s, t, _ = time_form(prs, steps, warmup)
+        from paper_2204_01133_amd import binding
+        forms[prec + "_batched"] = {"value": pts * stages * steps / t, "ms_per_step": t * 1000.0 / steps,
+                                    "launches_per_step": s.query(binding.Q_NUM_GROUPS),
+                                    "tiles": s.query(binding.Q_NUM_TILES)}
+    line = {"metric": "grid-point RK-stage updates/s", "unit": "grid-point RK-stage updates/s",
+            "config": {"workload": desc, "problems": len(base), "total_points": pts, "stages": stages,
+                       "form": "at_batch_step, HIP graph of 50 steps"},
+            "steps": steps, "warmup": warmup, "data": "synthetic", "forms": forms}
+    print(json.dumps(line))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only-headline", action="store_true",
                     help="time only the headline FP32 batched form (profiler runs)")
     ap.add_argument("--sample", type=int, default=128, help="problems in the oracle sample")
+    ap.add_argument("--config", default="c3", choices=["c3"] + sorted(OTHER_CONFIGS),
+                    help="c3 (default): the headline line; others: timing of both forms only")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the AT batch shards by "
@@ -133,10 +176,14 @@ def main():
         print("no GPU visible: libat has no CPU path", file=sys.stderr)
         sys.exit(1)
 
+    if args.config != "c3":
+        run_other(args.config, args.steps, args.warmup)
+        return
+
     base = W.batched_adr_c3()
     S = 4
     total_pts = W.total_points(base)
-    K, Wm = args.steps, args.warmup
+    K, Wm = args.steps, warmup_steps(args.warmup, args.steps)
 
     # headline: FP32 compensated, batched + graph
     prs32 = [p.replace(precision="fp32c") for p in base]

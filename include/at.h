@@ -97,7 +97,9 @@ typedef struct at_problem_desc {
 /*
  * Launch options (all 0 = defaults chosen by the planner).
  *   tile_points     largest number of points of one tile (work item); PEs are
- *                   packed whole into tiles, a PE may not exceed it.
+ *                   packed whole into tiles, a PE may not exceed it.  By default
+ *                   the small-tile capacity, with PEs packed only up to about two
+ *                   tiles per compute unit for workloads too small to fill the GPU.
  *   persistent      batched form: 1 = persistent grid (grid-stride over the
  *                   work list), 0 = one workgroup per tile, -1 = planner's choice.
  *   grid_per_cu     persistent grid size = grid_per_cu x 256 compute units.

@@ -195,6 +195,12 @@ int make_plan(const at_problem_desc* probs, int n_probs, const at_run_opts* opts
         kl.ppt = ppt_large(pi.key.kind, pi.key.f32);
         const int tsmall = BLOCK * ks.ppt, tlarge = BLOCK * kl.ppt;
         const int target = plan.opts.tile_points > 0 ? std::min(plan.opts.tile_points, tsmall) : tsmall;
+        // PEs are packed up to `pack` points: the target, lowered by default for small
+        // workloads so that there are about two tiles per compute unit (256 on MI355X)
+        // when the PEs allow it (a tile always takes at least one whole PE)
+        const int64_t spread = (plan.total_points + 2 * 256 - 1) / (2 * 256);
+        const int pack = plan.opts.tile_points > 0 ? target
+                                                   : (int)std::min<int64_t>(target, std::max<int64_t>(1, spread));
         Tile cur{b, 0, 0, 0, 0};
         auto pe_lo = [&](int64_t k) { return (k * d.n) / d.p; };
         for (int64_t k = 0; k < d.p; ++k) {
@@ -207,7 +213,7 @@ int make_plan(const at_problem_desc* probs, int n_probs, const at_run_opts* opts
                 large[b].push_back(Tile{b, (int32_t)k, 1, (int32_t)np, pe_lo(k)});
                 continue;
             }
-            bool fits = cur.npe > 0 && cur.npts + np <= target;
+            bool fits = cur.npe > 0 && cur.npts + np <= pack;
             if (fits) {
                 int64_t lds, rec;
                 variant_sizes(ks, (int)(cur.npts + np), cur.npe + 1, pi.J, &lds, &rec);
