@@ -771,10 +771,12 @@ AT_HD AT_FI void iface_flux(const QV<C>& L, const PhysP& P, int64_t e) {
     const LR al = a0 > a1 ? a0 : a1;
     const LR eps = LR(P.eps);
     const LR h = LR(0.5);
+#pragma unroll
     for (int f = 0; f < C::F; ++f) {
         const View<LR>& Q = L.g[f];
         const View<LR>& Cf = L.g[C::F + f];
         LR fp[5], fm[5];
+#pragma unroll
         for (int m = 0; m < 5; ++m) {
             fp[m] = h * (Cf[e - 2 + m] + al * Q[e - 2 + m]);
             fm[m] = h * (Cf[e + 3 - m] - al * Q[e + 3 - m]);
@@ -841,6 +843,7 @@ AT_HD AT_FI void rhs_at(const QV<C>& L, const PhysP& P, int64_t e, const typenam
         K[3] = -(d1<C>(L.g[3], e) * idx) + LR(P.rhoD) * Yxx + LR(arrhenius(P, qd));
     } else {  // WENO kinds
         const LR idx = LR(P.inv_dx);
+#pragma unroll
         for (int f = 0; f < C::F; ++f) K[f] = -((L.flux[f][e] - L.flux[f][e - 1]) * idx);
         if constexpr (C::KIND == K_REUL) {
             double qd[4] = {(double)q[0], (double)q[1], (double)q[2], (double)q[3]};
