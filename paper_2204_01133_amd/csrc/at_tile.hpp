@@ -793,11 +793,20 @@ AT_HD AT_FI void iface_flux(const QV<C>& L, const PhysP& P, int64_t e) {
 // to zero), hi and lo differences taken separately (hi - hi exact for neighbouring values)
 template <class C>
 AT_HD AT_FI float rhs_adr_hilo(const QV<C>& L, const PhysP& P, int64_t e, float hc, float lc) {
+    // every LDS read first (adjacent positions, so that they pair), then the arithmetic
+    float hp[C::H], hm[C::H], lp[C::H], lm[C::H];
+#pragma unroll
+    for (int o = 1; o <= C::H; ++o) {
+        hm[o - 1] = L.g[0][e - o];
+        lm[o - 1] = L.glo[e - o];
+        hp[o - 1] = L.g[0][e + o];
+        lp[o - 1] = L.glo[e + o];
+    }
     float k = 0.f;
 #pragma unroll
     for (int o = 1; o <= C::H; ++o) {
-        const float dp = (L.g[0][e + o] - hc) + (L.glo[e + o] - lc);
-        const float dm = (L.g[0][e - o] - hc) + (L.glo[e - o] - lc);
+        const float dp = (hp[o - 1] - hc) + (lp[o - 1] - lc);
+        const float dm = (hm[o - 1] - hc) + (lm[o - 1] - lc);
         k += P.lpf[o - 1] * dp;
         k += P.lmf[o - 1] * dm;
     }
