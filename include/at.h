@@ -101,8 +101,10 @@ typedef struct at_problem_desc {
  *                   the small-tile capacity, with PEs packed only up to about two
  *                   tiles per compute unit for workloads too small to fill the GPU.
  *   persistent      batched form: 1 = persistent grid (grid-stride over the
- *                   work list), 0 = one workgroup per tile, -1 = planner's choice.
- *   grid_per_cu     persistent grid size = grid_per_cu x 256 compute units.
+ *                   work list), 0 = one workgroup per tile, -1 = planner's choice
+ *                   (one workgroup per tile, which measured faster everywhere).
+ *   grid_per_cu     persistent grid size = grid_per_cu x 256 compute units
+ *                   (0 = 6, the workgroups per CU of the default LDS budget).
  *   graph_steps     batched form: steps per captured HIP graph (0 = plain launches).
  *   xcd_remap       1 = XCD-aware tile order (consecutive tiles on one XCD).
  *   log_steps       capacity, in steps, of the device delay log (0 = off).

@@ -1,0 +1,57 @@
+"""The planner's tiling rules (host code, run through the CPU build of the library).
+
+- Tiles hold whole PEs.  A workload too small to fill the GPU is spread to about
+  two tiles per compute unit, as far as its PEs allow (one PE per tile at most).
+- The default LDS per tile is 26 KiB for the FP32 scalar finite-difference kernels
+  of halo width up to 2 (6 workgroups per CU) and 40 KiB otherwise (4 per CU); an
+  explicit budget is respected; no launch exceeds the 160 KiB of a CU.
+"""
+import pytest
+
+import at_workloads as W
+
+at_emu = pytest.importorskip("at_emu")
+
+Q_TILES, Q_GROUPS, Q_POINTS, Q_LDS = 1, 2, 3, 6
+
+
+def _plan(prs, **opts):
+    return at_emu.Emu(prs, **opts)
+
+
+@pytest.mark.parametrize("prec", ["fp32c", "fp64"])
+def test_small_workloads_one_pe_per_tile(prec):
+    for pr in (W.adv_diff_c1(), W.reactive_ns_c2()):
+        e = _plan([pr.replace(precision=prec)])
+        assert e.query(Q_TILES) == pr.p, (pr.pde, e.query(Q_TILES))
+
+
+def test_large_batch_packs_several_pes_per_tile():
+    prs = W.batched_adr_c3(n_problems=512)
+    e = _plan([p.replace(precision="fp32c") for p in prs])
+    assert e.query(Q_POINTS) == W.total_points(prs)
+    # about two tiles per CU would be 512; the LDS budget, not the spread, sets the size
+    assert e.query(Q_TILES) < sum(p.p for p in prs)
+
+
+@pytest.mark.parametrize("prec,budget", [("fp32c", 26 * 1024), ("fp64", 40 * 1024)])
+def test_default_lds_budget(prec, budget):
+    prs = W.batched_adr_c3(n_problems=512)
+    e = _plan([p.replace(precision=prec) for p in prs])
+    assert e.query(Q_LDS) <= budget
+    assert e.query(Q_LDS) > budget // 2          # tiles are packed up to it
+
+
+def test_explicit_lds_budget_respected():
+    # PEs are packed up to the budget; a tile of one PE may exceed it
+    prs = [p.replace(precision="fp32c") for p in W.batched_adr_c3(n_problems=512)]
+    small = _plan(prs, lds_budget=16 * 1024)
+    large = _plan(prs, lds_budget=40 * 1024)
+    assert small.query(Q_TILES) > large.query(Q_TILES)
+    assert small.query(Q_LDS) <= large.query(Q_LDS) <= 40 * 1024
+
+
+def test_explicit_tile_points_respected():
+    pr = W.adv_diff_c1(n=4096, p=64).replace(precision="fp32c")
+    e = _plan([pr], tile_points=256)
+    assert e.query(Q_TILES) == 4096 // 256
