@@ -168,7 +168,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the AT batch shards by "
-              "problem across GPUs with no communication, see DESIGN.md", file=sys.stderr)
+              "problem across GPUs with no communication (one plan and ring per GPU)", file=sys.stderr)
         sys.exit(2)
 
     import torch

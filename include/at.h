@@ -38,7 +38,7 @@ extern "C" {
 enum at_status {
     AT_OK = 0,
     AT_EINVAL = -1,        /* bad descriptor, size or argument                          */
-    AT_EUNSUPPORTED = -2,  /* valid combination this build does not run (e.g. PE too big) */
+    AT_EUNSUPPORTED = -2,  /* valid combination the library does not run (e.g. PE too big) */
     AT_ESTATE = -3,        /* call order (not bound, state not set, mid-step)           */
     AT_EHIP = -4,          /* HIP runtime error; text in at_last_error                  */
     AT_ESTALE = -5,        /* delay override asks for data older than the ring holds    */
