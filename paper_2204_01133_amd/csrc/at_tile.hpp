@@ -344,9 +344,9 @@ struct Layout {
         NW = npe_max + 1;
         EXW = NW * C::WL;
         if (C::HILO) EXW = (EXW + 63) & ~int64_t(63);   // whole wave-sized chunks (direct copy)
-        // per PE side: the delayed strips of jmax levels, or (FP32 scalar kind) their
+        // per PE side: the delayed strips of jmax levels, or (scalar FD kind) their
         // extrapolation to level n, one level's worth
-        const int64_t jl = C::HILO ? 1 : jmax;
+        const int64_t jl = C::KIND == K_ADR ? 1 : jmax;
         SOREC = jl * C::S * C::H * C::F;
         // FP32 scalar kind: no raw range (own points go to registers, windows straight
         // into the window region)
@@ -380,7 +380,7 @@ struct Layout {
         o_SOhi = o;  o += C::F32 ? align16(2 * (int64_t)npe_max * jl * C::H * C::F * 4) : 0;
         o_pelo = o;  o += align16((npe_max + 1) * 4);
         o_keff = o;  o += align16(2 * (int64_t)npe_max * 4);
-        o_wt = o;    o += C::HILO ? 0 : align16(16 * JMAXW * 8);   // extrapolation weights [k][l]
+        o_wt = o;    o += C::KIND == K_ADR ? 0 : align16(16 * JMAXW * 8);   // extrapolation weights [k][l]
         total = o;
     }
 };
@@ -576,7 +576,7 @@ struct Lds {
     View<float> rl[C::F];      // raw FP32 lo
     int EXM, EXW, SOREC, jmax;
     AT_HD void init(unsigned char* base, const Layout<C>& Lo, int npe_max, int jm) {
-        if (C::HILO) jm = 1;    // one extrapolated level per side
+        if (C::KIND == K_ADR) jm = 1;    // one extrapolated level per side
         EXM = (int)Lo.EXM; EXW = (int)Lo.EXW; SOREC = (int)Lo.SOREC; jmax = jm;
         const int64_t nm = Lo.EXM, nw = Lo.EXW;
         for (int par = 0; par < 2; ++par) {
@@ -621,7 +621,7 @@ struct Lds {
         SOhi = View<float>{(float*)(base + Lo.o_SOhi), C::F32 ? 2 * (int64_t)npe_max * jm * C::H * C::F : 0};
         pelo = View<int>{(int*)(base + Lo.o_pelo), npe_max + 1};
         keff = View<int>{(int*)(base + Lo.o_keff), 2 * (int64_t)npe_max};
-        wt = View<double>{(double*)(base + Lo.o_wt), C::HILO ? 0 : 16 * JMAXW};
+        wt = View<double>{(double*)(base + Lo.o_wt), C::KIND == K_ADR ? 0 : 16 * JMAXW};
         for (int f = 0; f < C::F; ++f) {
             rh[f] = View<L>{(L*)(base + Lo.o_rh) + f * Lo.EXR, Lo.EXR};
             rl[f] = View<float>{(float*)(base + Lo.o_rl) + f * Lo.EXR, C::F32 ? Lo.EXR : 0};
@@ -1147,6 +1147,32 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const AT_CONST Pr
 #pragma unroll
         for (int r = 0; r < nrec; ++r) L.SO[side_idx * L.SOREC + r] = lo[r];
     };
+    // FP64 scalar kind: the halo of every stage, extrapolated once per step (the
+    // weighted sum over the levels, level order, as the extrapolation of the other
+    // kinds takes it).  Levels below nreg are in registers, the others are loaded here.
+    auto hq_put64 = [&](int side_idx, int ke, int jeff, int nreg, const LR (&rv)[JPR][nrec]) {
+        const int kw = ke == 0 ? 1 : J;          // the weights of delay 0 are one level's
+        LR acc[nrec];
+#pragma unroll
+        for (int r = 0; r < nrec; ++r) acc[r] = LR(WTAB.w[kw][ke][0]) * rv[0][r];
+#pragma unroll
+        for (int l = 1; l < JM; ++l) {
+            if (l >= jeff) continue;
+            LR v[nrec];
+            float vh[nhi];
+            if (l < JPR && l < nreg) {
+#pragma unroll
+                for (int r = 0; r < nrec; ++r) v[r] = rv[l < JPR ? l : 0][r];
+            } else {
+                ring_ld(side_idx, ke, l, v, vh);
+            }
+            const LR w = LR(WTAB.w[kw][ke][l]);
+#pragma unroll
+            for (int r = 0; r < nrec; ++r) acc[r] += w * v[r];
+        }
+#pragma unroll
+        for (int r = 0; r < nrec; ++r) L.SO[side_idx * L.SOREC + r] = acc[r];
+    };
     rt.each([&](int tid, TS<C>& ts) {
         const int nraw = t.npts + 2 * SH;
         AT_CHECK(nraw <= nth * (PPT + 1), "raw range", nraw, nth * (PPT + 1));
@@ -1246,7 +1272,7 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const AT_CONST Pr
         }
         for (int k = first_item(tid, nth, 3); k <= t.npe; k += nth)
             L.pelo[k] = (int)(pe_offset(t.pe0 + k) - t.lo);
-        if (!C::HILO && tid < 16 * JMAXW) {   // weights for delay k (J levels; k = 0 uses one level)
+        if (C::KIND != K_ADR && tid < 16 * JMAXW) {   // weights for delay k (J levels; k = 0 uses one level)
             const int k = tid / JMAXW, l = tid % JMAXW;
             L.wt[tid] = l < JM ? WTAB.w[k == 0 ? 1 : J][k][l] : 0.0;
         }
@@ -1271,6 +1297,16 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const AT_CONST Pr
                 if (jeff == 0) continue;
                 ring_ld(side_idx, ke, 0, rv[0], rvh[0]);
                 hq_put(side_idx, ke, jeff, 1, rv, rvh, wl);
+            }
+        } else if constexpr (C::KIND == K_ADR) {
+            if (has0 && jeff0 > 0) hq_put64(si0, ke0, jeff0, JPF, rv);
+            // further PE sides (tiles of more than nth / 2 PEs)
+            for (int side_idx = si0 + nth; side_idx < 2 * t.npe; side_idx += nth) {
+                int ke;
+                const int jeff = side_delays(side_idx, ke);
+                if (jeff == 0) continue;
+                ring_ld(side_idx, ke, 0, rv[0], rvh[0]);
+                hq_put64(side_idx, ke, jeff, 1, rv);
             }
         } else {
             if (has0) {
@@ -1399,6 +1435,8 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const AT_CONST Pr
             // extrapolated in the load phase
             if (s == s0) M.g[0][e] = L.SOhi[side_idx * H * F + h * F];
             M.glo[e] = L.SO[sob + (s * H + h) * F];
+        } else if constexpr (C::KIND == K_ADR) {
+            M.g[0][e] = L.SO[sob + (s * H + h) * F];   // extrapolated in the load phase
         } else {
             const int ke = L.keff[side_idx];
             const int jeff = ke == 0 ? 1 : J;
