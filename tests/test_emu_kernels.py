@@ -96,3 +96,14 @@ def test_emu_override_stale_rejected():
     e = at_emu.Emu([pr], override_steps=4)
     with pytest.raises(at_emu.EmuError):
         e.set_override(0, np.full((2, 4, 2), 3, np.uint8), 0)
+
+
+@pytest.mark.parametrize("prec", ["fp32c", "fp64"])
+def test_emu_tiles_of_many_pes(prec):
+    """Tiles of more PE sides than threads (several sides per thread in the load
+    phase): 512 PEs of 4 points packed into 2-3 tiles by an explicit budget."""
+    pr = with_precision(W.adv_diff_c1(n=2048, p=512, kmax=2), prec)
+    e = at_emu.Emu([pr], lds_budget=160 * 1024, tile_points=2048)
+    assert e.query(1) <= 3
+    e.step(12)
+    assert norm_err(pr, e.state(0), _oracle(pr, 12).state()) < tol(prec)

@@ -222,3 +222,14 @@ def test_full_c5_first_steps(torch):
     s = solver([pr])
     s.batch_step(5)
     assert norm_err(pr, s.state(0), _oracle(pr, 5).state()) < tol("fp32c")
+
+
+@pytest.mark.parametrize("prec", ["fp32c", "fp64"])
+def test_tiles_of_many_pes(torch, prec):
+    """Tiles of more PE sides than threads (several sides per thread in the load
+    phase): 512 PEs of 4 points packed into 2-3 tiles by an explicit budget."""
+    pr = with_precision(W.adv_diff_c1(n=2048, p=512, kmax=2), prec)
+    s = solver([pr], lds_budget=160 * 1024, tile_points=2048)
+    assert s.query(1) <= 3
+    s.batch_step(12)
+    assert norm_err(pr, s.state(0), _oracle(pr, 12).state()) < tol(prec)
