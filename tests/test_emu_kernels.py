@@ -107,3 +107,14 @@ def test_emu_tiles_of_many_pes(prec):
     assert e.query(1) <= 3
     e.step(12)
     assert norm_err(pr, e.state(0), _oracle(pr, 12).state()) < tol(prec)
+
+
+@pytest.mark.parametrize("prec", ["fp32c", "fp64"])
+@pytest.mark.parametrize("levels,scheme", [(4, "fd4"), (5, "fd8")])
+def test_emu_more_extrapolation_levels(prec, levels, scheme):
+    """J above the default (at_levels): the load phase takes the levels beyond those
+    it holds in registers from the ring one at a time."""
+    pr = with_precision(W.adv_diff_c1(n=256, p=8, kmax=3, scheme=scheme), prec).replace(at_levels=levels)
+    e = at_emu.Emu([pr])
+    e.step(12)
+    assert norm_err(pr, e.state(0), _oracle(pr, 12).state()) < tol(prec)

@@ -233,3 +233,14 @@ def test_tiles_of_many_pes(torch, prec):
     assert s.query(1) <= 3
     s.batch_step(12)
     assert norm_err(pr, s.state(0), _oracle(pr, 12).state()) < tol(prec)
+
+
+@pytest.mark.parametrize("prec", ["fp32c", "fp64"])
+@pytest.mark.parametrize("levels,scheme", [(4, "fd4"), (5, "fd8")])
+def test_more_extrapolation_levels(torch, prec, levels, scheme):
+    """J above the default (at_levels): the load phase takes the levels beyond those
+    it holds in registers from the ring one at a time."""
+    pr = with_precision(W.adv_diff_c1(n=256, p=8, kmax=3, scheme=scheme), prec).replace(at_levels=levels)
+    s = solver([pr])
+    s.batch_step(12)
+    assert norm_err(pr, s.state(0), _oracle(pr, 12).state()) < tol(prec)
