@@ -244,3 +244,14 @@ def test_more_extrapolation_levels(torch, prec, levels, scheme):
     s = solver([pr])
     s.batch_step(12)
     assert norm_err(pr, s.state(0), _oracle(pr, 12).state()) < tol(prec)
+
+
+@pytest.mark.parametrize("prec", ["fp32c", "fp64"])
+@pytest.mark.parametrize("n,p", [(12, 3), (9, 1), (15, 5)])
+def test_domains_shorter_than_a_window(torch, prec, n, p):
+    """Periodic domains shorter than a boundary window (N < S H): the windows wrap
+    round the domain more than once."""
+    pr = with_precision(W.adv_diff_c1(n=n, p=p, kmax=2), prec)
+    s = solver([pr])
+    s.batch_step(10)
+    assert norm_err(pr, s.state(0), _oracle(pr, 10).state()) < tol(prec)
