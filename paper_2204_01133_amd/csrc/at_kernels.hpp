@@ -5,6 +5,9 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <atomic>
+#include <cstdint>
+
 #include "at_plan.hpp"
 #include "at_variants.hpp"
 
@@ -73,12 +76,18 @@ void at_tile_kernel(KArgs a) {
 
 template <class C, bool STEP>
 hipError_t launch_form(const KArgs& a, int grid, hipStream_t s) {
-    static bool attr_done = false;
-    if (!attr_done) {
-        hipError_t e = hipFuncSetAttribute((const void*)at_tile_kernel<C, STEP>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    // the dynamic-LDS limit is a property of the kernel on each device: raised once per
+    // device (the current one, which the stream belongs to); safe under concurrent launches
+    static std::atomic<uint64_t> attr_done{0};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    const uint64_t bit = dev < 64 ? uint64_t(1) << dev : 0;
+    if (!(attr_done.load(std::memory_order_acquire) & bit)) {
+        e = hipFuncSetAttribute((const void*)at_tile_kernel<C, STEP>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         if (e != hipSuccess) return e;
-        attr_done = true;
+        attr_done.fetch_or(bit, std::memory_order_acq_rel);
     }
     hipLaunchKernelGGL((at_tile_kernel<C, STEP>), dim3(grid), dim3(BLOCK), (size_t)a.lds_bytes, s, a);
     return hipGetLastError();
