@@ -224,6 +224,46 @@ def test_full_c5_first_steps(torch):
     assert norm_err(pr, s.state(0), _oracle(pr, 5).state()) < tol("fp32c")
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32c"])
+def test_full_c2_first_steps(torch, prec):
+    """The reactive NS flame at its full size (N 8192, P 64, FD8 with the 3-level halo,
+    four fields, one-step Arrhenius chemistry): state and delay logs of 20 steps."""
+    pr = with_precision(W.reactive_ns_c2(), prec)
+    steps = 20
+    s = solver([pr], log_steps=steps + 1)
+    s.batch_step(steps)
+    o = _oracle(pr, steps)
+    assert norm_err(pr, s.state(0), o.state()) < tol(prec)
+    d1, e1 = s.delays(0, 0, steps)
+    d2, e2 = o.delays(0, steps)
+    assert np.array_equal(d1, d2) and np.array_equal(e1, e2)
+
+
+_C5B_REF = {}
+
+
+@pytest.mark.parametrize("prec", ["fp32c", "fp64"])
+def test_full_c5_batch_sampled(torch, prec):
+    """The 256-tube detonation batch (19.2 M points) in the launch configuration of its
+    timing: one launch per step, replayed from a graph of 50 steps.  The smallest and the
+    largest tube against the oracle after those 50 steps (the FP32 form within its bound for
+    the reacting front); every tube finite with positive density."""
+    prs = [p.replace(precision=prec) for p in W.detonation_batch_c5()]
+    steps = 50
+    s = solver(prs, graph_steps=steps, log_steps=4)
+    s.batch_step(steps)
+    ns = np.array([p.n for p in prs])
+    for b in sorted({int(ns.argmin()), int(ns.argmax())}):
+        if b not in _C5B_REF:
+            _C5B_REF[b] = _oracle(prs[b], steps).state()
+        err = norm_err(prs[b], s.state(b), _C5B_REF[b])
+        print(f"tube {b} N {prs[b].n} {prec}: {err:.3e}", flush=True)
+        assert err < tol(prec, prs[b]), b
+    for b in range(0, len(prs), 15):
+        u = s.state(b)
+        assert np.isfinite(u).all() and u[0].min() > 0.0, b
+
+
 @pytest.mark.parametrize("prec", ["fp32c", "fp64"])
 def test_tiles_of_many_pes(torch, prec):
     """Tiles of more PE sides than threads (several sides per thread in the load
