@@ -286,10 +286,11 @@ def main():
             "value": cpu_rate,
             "unit": "grid-point RK-stage updates/s",
             "cores": workers,
+            "per_core": sample_pts * S * total_steps / ocpu if ocpu > 0 else None,
             "kind": "oracle",
             "sample": f"{len(idx)} of {len(base)} problems (every {len(base) // len(idx)}th, "
                       f"{sample_pts} points), {total_steps} steps, FP64 serial C oracle, "
-                      f"{workers} processes, {ocpu:.1f} s CPU",
+                      f"{workers} processes, {ocpu:.1f} s CPU; per_core = updates per CPU-second of one process",
         },
         "forms": {
             "fp32c_batched": {"value": value, "ms_per_step": ms_step, "max_norm_err_vs_oracle": err32,
