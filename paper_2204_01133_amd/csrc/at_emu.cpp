@@ -259,6 +259,8 @@ int64_t emu_query(void* ctx, int key) {
     case AT_Q_NUM_GROUPS: return (int64_t)c.plan.groups.size();
     case AT_Q_TOTAL_POINTS: return c.plan.total_points;
     case AT_Q_STATE_BYTES: return c.plan.state_bytes_per_step;
+    case AT_Q_STRIP_BYTES: return c.plan.strip_bytes_per_step;
+    case AT_Q_NUM_PES: return c.plan.total_pes;
     case AT_Q_LDS_BYTES: {
         int64_t m = 0;
         for (const Group& g : c.plan.groups) m = g.lds_bytes > m ? g.lds_bytes : m;

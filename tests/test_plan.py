@@ -55,3 +55,26 @@ def test_explicit_tile_points_respected():
     pr = W.adv_diff_c1(n=4096, p=64).replace(precision="fp32c")
     e = _plan([pr], tile_points=256)
     assert e.query(Q_TILES) == 4096 // 256
+
+
+Q_STATE, Q_STRIP, Q_PES = 4, 7, 8
+
+
+@pytest.mark.parametrize("prec", ["fp32c", "fp32", "fp64"])
+@pytest.mark.parametrize("make,S,H,F", [(lambda: W.batched_adr_c3(n_problems=64), 4, 2, 1),
+                                        (lambda: [W.reactive_ns_c2()], 4, 4, 4),
+                                        (lambda: [W.euler_sod_c4(n=4096, p=16)], 3, 3, 3)])
+def test_algorithmic_bytes_follow_the_layout(prec, make, S, H, F):
+    """The byte counts behind the roofline figures.  The state is read and written once
+    per point and field: 8 B for FP64 and for FP32 hi + lo, 4 B for FP32.  Every PE
+    side writes one ring record of the stage values at its H halo points: 8*S*H*F bytes
+    in FP64, 4*(S+1)*H*F in the FP32 forms (the low parts of stage 1 ride along)."""
+    prs = [p.replace(precision=prec) for p in make()]
+    e = _plan(prs)
+    s_state = {"fp64": 8, "fp32c": 8, "fp32": 4}[prec]
+    rec = 8 * S * H * F if prec == "fp64" else 4 * (S + 1) * H * F
+    npts = sum(p.n for p in prs)
+    npes = sum(p.p for p in prs)
+    assert e.query(Q_PES) == npes
+    assert e.query(Q_STATE) == 2 * F * npts * s_state
+    assert e.query(Q_STRIP) == 2 * npes * rec
