@@ -29,6 +29,11 @@ struct at_ctx {
     std::vector<ProbDev> pd;
     std::vector<ProbDev> tpd_pm, tpd_bt;   // per-tile descriptor copies (host staging)
     int num_cus = 256;
+    // the groups of a batched step run concurrently: group 0 on the caller's stream, every
+    // other group on a stream of its own, forked from and joined back into the caller's
+    // stream with events (fork event first, then one join event per side stream)
+    std::vector<hipStream_t> side;
+    std::vector<hipEvent_t> ev;
     // graph of graph_steps batched steps
     hipGraphExec_t gexec = nullptr;
     hipGraph_t graph = nullptr;
@@ -72,13 +77,13 @@ __global__ void k_join(const float* __restrict__ hi, const float* __restrict__ l
 __global__ void k_set_step(int64_t* d, int64_t v) { *d = v; }
 __global__ void k_add_step(int64_t* d, int64_t v) { *d += v; }
 
-int launch_key(at_ctx* c, const VariantKey& k, const KArgs& a, int grid) {
+int launch_key(at_ctx* c, const VariantKey& k, const KArgs& a, int grid, hipStream_t s) {
     if (grid <= 0 || a.ntiles <= 0) return AT_OK;
     hipError_t e = hipSuccess;
-    bool ok = launch_adr(k, a, grid, c->stream, &e) || launch_adr32(k, a, grid, c->stream, &e) ||
-              launch_rns(k, a, grid, c->stream, &e) || launch_rns32(k, a, grid, c->stream, &e) ||
-              launch_wscal(k, a, grid, c->stream, &e) || launch_eul(k, a, grid, c->stream, &e) ||
-              launch_reul(k, a, grid, c->stream, &e);
+    bool ok = launch_adr(k, a, grid, s, &e) || launch_adr32(k, a, grid, s, &e) ||
+              launch_rns(k, a, grid, s, &e) || launch_rns32(k, a, grid, s, &e) ||
+              launch_wscal(k, a, grid, s, &e) || launch_eul(k, a, grid, s, &e) ||
+              launch_reul(k, a, grid, s, &e);
     if (!ok) return fail(c, AT_EUNSUPPORTED, "kernel variant not compiled");
     if (e != hipSuccess) return hip_fail(c, e, "tile kernel launch");
     return AT_OK;
@@ -121,9 +126,41 @@ int check_ready(at_ctx* c) {
     return AT_OK;
 }
 
-// one batched step (all groups, all stages) with step counter n or from the device counter
+// side streams and events for concurrent groups (created once per context)
+int make_side_streams(at_ctx* c) {
+    const size_t ng = c->plan.groups.size();
+    while (c->side.size() + 1 < ng) {
+        hipStream_t st = nullptr;
+        HIPCHK(c, hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+        c->side.push_back(st);
+    }
+    while (ng > 1 && c->ev.size() < ng) {
+        hipEvent_t e = nullptr;
+        HIPCHK(c, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        c->ev.push_back(e);
+    }
+    return AT_OK;
+}
+
+void free_side_streams(at_ctx* c) {
+    for (hipStream_t st : c->side) (void)hipStreamDestroy(st);
+    for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+    c->side.clear();
+    c->ev.clear();
+}
+
+// one batched step (all groups, all stages) with step counter n or from the device counter.
+// The tiles of a step are independent (they read level n and older, and write level n+1
+// and their own ring records of level n), so the groups run concurrently.
 int batched_step_launches(at_ctx* c, const int64_t* step_ptr, int64_t step_off) {
-    for (const Group& g : c->plan.groups) {
+    const size_t ng = c->plan.groups.size();
+    if (ng > 1) {
+        if (c->side.size() + 1 < ng || c->ev.size() < ng) return fail(c, AT_ESTATE, "side streams missing");
+        HIPCHK(c, hipEventRecord(c->ev[0], c->stream));
+        for (size_t i = 1; i < ng; ++i) HIPCHK(c, hipStreamWaitEvent(c->side[i - 1], c->ev[0], 0));
+    }
+    for (size_t gi = 0; gi < ng; ++gi) {
+        const Group& g = c->plan.groups[gi];
         KArgs a = base_args(c, g);
         a.tiles = (const Tile*)(c->ws + c->plan.off_tiles_bt) + g.t0;
         a.tprobs = (const ProbDev*)(c->ws + c->plan.off_tpd_bt) + g.t0;
@@ -138,8 +175,12 @@ int batched_step_launches(at_ctx* c, const int64_t* step_ptr, int64_t step_off) 
         const int persistent = c->plan.opts.persistent == 1 ? 1 : 0;
         const int per_cu = c->plan.opts.grid_per_cu > 0 ? c->plan.opts.grid_per_cu : 6;
         const int grid = persistent ? std::min(g.ntiles, per_cu * c->num_cus) : g.ntiles;
-        int rc = launch_key(c, g.key, a, grid);
+        int rc = launch_key(c, g.key, a, grid, gi == 0 ? c->stream : c->side[gi - 1]);
         if (rc) return rc;
+    }
+    for (size_t i = 1; i < ng; ++i) {
+        HIPCHK(c, hipEventRecord(c->ev[i], c->side[i - 1]));
+        HIPCHK(c, hipStreamWaitEvent(c->stream, c->ev[i], 0));
     }
     return AT_OK;
 }
@@ -218,6 +259,8 @@ int at_bind(at_ctx* c, void* d_workspace, size_t bytes, void* hip_stream) {
                              sizeof(Tile) * c->plan.tiles_pm.size(), hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(c->ws + c->plan.off_tiles_bt, c->plan.tiles_bt.data(),
                              sizeof(Tile) * c->plan.tiles_bt.size(), hipMemcpyHostToDevice, c->stream));
+    int rc = make_side_streams(c);
+    if (rc) return rc;
     c->bound = true;
     return upload_probs(c);
 }
@@ -283,7 +326,7 @@ int at_step(at_ctx* c, int n_steps) {
                 a.step_off = c->step;
                 a.s_begin = 0;
                 a.s_end = pi.S - 1;
-                rc = launch_key(c, g.key, a, cnt);
+                rc = launch_key(c, g.key, a, cnt, c->stream);
                 if (rc) return rc;
             }
         }
@@ -339,7 +382,7 @@ int at_rk_stage(at_ctx* c, int stage) {
         a.s_begin = stage - 1;
         a.s_end = stage - 1;
         a.flags |= KF_STAGE_IO;
-        rc = launch_key(c, g.key, a, g.ntiles);
+        rc = launch_key(c, g.key, a, g.ntiles, c->stream);
         if (rc) return rc;
     }
     c->stage = stage;
@@ -468,6 +511,7 @@ const char* at_last_error(const at_ctx* c) { return c ? c->err.c_str() : "no con
 void at_free(at_ctx* c) {
     if (!c) return;
     drop_graph(c);
+    free_side_streams(c);
     delete c;
 }
 

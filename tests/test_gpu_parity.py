@@ -91,6 +91,27 @@ def test_launch_forms_agree_bitwise(torch, prec):
             assert np.array_equal(a, b), (method, opts)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32c"])
+def test_kernel_groups_run_concurrently(torch, prec):
+    """Several kernel groups in one step (four kinds, and a problem whose 4096-point PEs
+    need the large-tile class): the groups of a batched step run on concurrent streams,
+    launched directly and from graphs, with the results of the plain form (one launch
+    per problem, in order) and of the oracle."""
+    prs = [W.adv_diff_c1(n=128, p=4, kmax=2), W.euler_sod_c4(n=256, p=4, kmax=2),
+           W.reactive_ns_c2(n=256, p=4), W.burgers_sweep(64, p=4, n_ref=64),
+           W.adv_diff_c1(n=8192, p=2, kmax=2)]
+    prs = [with_precision(p.replace(problem_id=i), prec) for i, p in enumerate(prs)]
+    steps = 12
+    assert solver(prs).query(2) >= 5           # kernel groups
+    ref = _run(prs, steps, "step")
+    for opts in ({}, {"graph_steps": 4}, {"graph_steps": 5, "persistent": 1}):
+        got = _run(prs, steps, "batch_step", **opts)
+        for a, b in zip(got, ref):
+            assert np.array_equal(a, b), opts
+    for b, pr in enumerate(prs):
+        assert norm_err(pr, ref[b], _oracle(pr, steps).state()) < tol(prec, pr), b
+
+
 def test_graph_replay_on_torch_stream(torch):
     prs, _ = batch_case()
     st = torch.cuda.Stream()
