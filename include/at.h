@@ -134,8 +134,10 @@ int at_init(const at_problem_desc* probs, int n_probs, const at_run_opts* opts, 
             size_t* workspace_bytes);
 
 /* Hand over the caller-owned device workspace (>= workspace_bytes, 256-byte
- * aligned) and the HIP stream (hipStream_t, NULL = default stream).  Uploads
- * the problem tables (stream-ordered).  Errors: AT_EINVAL, AT_EHIP. */
+ * aligned) and the HIP stream (hipStream_t, NULL = default stream) on the
+ * current device.  Uploads the problem tables (stream-ordered) and creates the
+ * side streams and events of at_batch_step (one per kernel variant after the
+ * first).  Errors: AT_EINVAL, AT_EHIP. */
 int at_bind(at_ctx* ctx, void* d_workspace, size_t bytes, void* hip_stream);
 
 /* Set problem `prob`'s level-0 state: F x N doubles (structure of arrays,
@@ -159,7 +161,11 @@ int at_step(at_ctx* ctx, int n_steps);
 
 /* Batched form: n_steps steps, each one launch per kernel variant over the
  * work list of all problems (persistent or one workgroup per tile), replayed
- * from captured HIP graphs of graph_steps steps when enabled. */
+ * from captured HIP graphs of graph_steps steps when enabled.  The launches of
+ * one step run concurrently: the first on the context's stream, the others on
+ * library-owned streams (created by at_bind, destroyed by at_free) that fork
+ * from it and join back into it with events, so the call stays ordered on the
+ * context's stream.  Errors: AT_ESTATE, AT_EINVAL, AT_EHIP. */
 int at_batch_step(at_ctx* ctx, int n_steps);
 
 /* Copy problem `prob`'s current state out as F x N doubles (hi + lo for the
