@@ -9,8 +9,9 @@ independent advection-diffusion-logistic problems, N log-uniform in
 One "step" = one RK time step (all 4 stages, delay draws, strip ring update)
 of all 4096 problems: one persistent/batched kernel launch, replayed from a
 HIP graph.  Timed form: FP32 with compensated (hi+lo) state.  Reported beside
-it: FP64 batched and FP64 plain (one launch per problem) on the same data,
-with the error of each against the FP64 oracle on sampled problems.
+it: FP64 batched, FP32 batched with a 4-byte state, and FP64 plain (one launch
+per problem) on the same data, with the error of each batched form against the
+FP64 oracle on sampled problems.
 
     python bench.py [--gpus 1] [--steps 1000] [--warmup 20]
     python bench.py --config {c1,c2,c4,c5,c5batch} --steps 100   # other configurations, timing only
@@ -216,6 +217,10 @@ def main():
     prs64 = [p.replace(precision="fp64") for p in base]
     s64, t64, _ = time_form(prs64, K, Wm)
     bytes64 = algorithmic_bytes_per_step(prs64, s64)
+    # FP32 batched with a 4-byte state (the low part is not kept across steps)
+    prsf = [p.replace(precision="fp32") for p in base]
+    sf, tf, _ = time_form(prsf, K, Wm)
+    bytesf = algorithmic_bytes_per_step(prsf, sf)
     kp = max(2, min(20, K // 50))
     _, tplain, _ = time_form(prs64, kp, 2, method="step", graph_steps=0)
 
@@ -229,12 +234,13 @@ def main():
         workers = max(1, min(16, os.cpu_count() or 1))
     sample_pts = sum(base[i].n for i in idx)
     if args.no_cpu_baseline:
-        err32 = err64 = None
+        err32 = err64 = errf = None
         cpu_rate, owall, ocpu = None, 0.0, 0.0
     else:
         refs, owall, ocpu = oracle_sample(base, idx, total_steps, workers)
         err32 = max(norm_err(s32.state(i), r) for i, r in zip(idx, refs))
         err64 = max(norm_err(s64.state(i), r) for i, r in zip(idx, refs))
+        errf = max(norm_err(sf.state(i), r) for i, r in zip(idx, refs))
         cpu_rate = sample_pts * S * total_steps / owall
 
     traffic = None
@@ -298,6 +304,12 @@ def main():
             "fp64_batched": {"value": total_pts * S * K / t64, "ms_per_step": t64 * 1000.0 / K,
                              "max_norm_err_vs_oracle": err64,
                              "hbm_gbs": bytes64["total"] / (t64 / K) / 1e9},
+            "fp32_batched": {"value": total_pts * S * K / tf, "ms_per_step": tf * 1000.0 / K,
+                             "max_norm_err_vs_oracle": errf,
+                             # the 4-byte state is rounded to FP32 once per step (at most 2^-24
+                             # of the field's scale each time)
+                             "stated_error_bound": max(2e-5, total_steps * 2.0 ** -24),
+                             "hbm_gbs": bytesf["total"] / (tf / K) / 1e9},
             "fp64_plain": {"value": total_pts * S * kp / tplain, "ms_per_step": tplain * 1000.0 / kp,
                            "launches_per_step": len(base)},
             "stated_error_bound": 2e-6,

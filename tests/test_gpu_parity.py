@@ -214,7 +214,7 @@ def test_full_c1(torch):
     assert np.array_equal(s.delays(0, 0, pr.steps)[0], o.delays(0, pr.steps)[0])
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32c"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32c", "fp32"])
 def test_full_c3_sampled(torch, prec):
     prs = [p.replace(precision=prec) for p in W.batched_adr_c3()]
     steps = prs[0].steps
@@ -223,8 +223,10 @@ def test_full_c3_sampled(torch, prec):
     ns = np.array([p.n for p in prs])
     pick = sorted({int(ns.argmin()), int(ns.argmax()), 0, 1, 2047, 4095,
                    int(np.argmax([p.kmax for p in prs])), int(np.argmax([p.p for p in prs]))})
+    # the FP32 form rounds its 4-byte state once per step: at most 2^-24 of the scale each
+    bound = max(tol(prec), steps * 2.0 ** -24) if prec == "fp32" else tol(prec)
     for b in pick:
-        assert norm_err(prs[b], s.state(b), _oracle(prs[b], steps).state()) < tol(prec), b
+        assert norm_err(prs[b], s.state(b), _oracle(prs[b], steps).state()) < bound, b
     # invariants over the whole batch: finite and bounded (logistic keeps u in (0, 1.1))
     for b in range(0, len(prs), 97):
         u = s.state(b)
