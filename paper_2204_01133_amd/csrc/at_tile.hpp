@@ -421,11 +421,11 @@ AT_HD AT_FI int draw_delay(const ProbDev& P, const AT_CONST uint64_t* cdf, uint6
     return k;
 }
 
-// Lagrange weights from levels -k..-k-J+1 to 0: w_l = prod_{m!=l} (k+m)/(m-l), exact
-// integers; fixed-size loops (JM >= J) so that w stays in registers.
+// AT time-extrapolation weights (Sec. 2.2, Table A): Lagrange weights from levels
+// -k..-k-J+1 to 0, w_l = prod_{m!=l} (k+m)/(m-l), exact integers, tabulated at compile
+// time: WTAB.w[J][k][l], J = 1..JM, k = 0..15.
 constexpr int JM = 6;
 
-// The same weights tabulated at compile time: WTAB.w[J][k][l], J = 1..JM, k = 0..15.
 struct WeightTable {
     double w[JM + 1][16][8];
 };
@@ -449,19 +449,6 @@ __constant__ constexpr WeightTable WTAB = make_weight_table();
 #else
 constexpr WeightTable WTAB = make_weight_table();
 #endif
-AT_HD AT_FI void lagrange_weights(int J, int k, double (&w)[JM]) {
-#pragma unroll
-    for (int l = 0; l < JM; ++l) {
-        int64_t num = 1, den = 1;
-#pragma unroll
-        for (int m = 0; m < JM; ++m) {
-            if (m == l || m >= J) continue;
-            num *= (int64_t)(k + m);
-            den *= (int64_t)(m - l);
-        }
-        w[l] = l < J ? (double)(num / den) : 0.0;
-    }
-}
 
 // ---------------------------------------------------------------------------
 // central finite-difference weights (textbook, order 2H)
