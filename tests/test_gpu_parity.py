@@ -112,6 +112,20 @@ def test_kernel_groups_run_concurrently(torch, prec):
         assert norm_err(pr, ref[b], _oracle(pr, steps).state()) < tol(prec, pr), b
 
 
+def test_autotuned_options_agree_bitwise(torch):
+    """The autotuner times candidate run options on the GPU; whatever it picks, the
+    result equals the default options' bit for bit."""
+    from paper_2204_01133_amd.autotune import autotune
+    prs, _ = batch_case()
+    res = autotune(prs, steps=8, graph_steps=4)
+    assert res["ms_per_step"] is not None and res["ms_per_step"] > 0
+    assert sum(ms is not None for _, ms in res["table"]) >= 5
+    ref = _run(prs, 13, "batch_step")
+    got = _run(prs, 13, "batch_step", **res["opts"])
+    for a, b in zip(got, ref):
+        assert np.array_equal(a, b), res["opts"]
+
+
 def test_graph_replay_on_torch_stream(torch):
     prs, _ = batch_case()
     st = torch.cuda.Stream()
