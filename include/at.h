@@ -114,9 +114,10 @@ typedef struct at_problem_desc {
  *                   default of the kernel: 26 KiB, 6 workgroups per compute unit,
  *                   for the FP32 scalar finite-difference kernels of order 2 and 4,
  *                   whose whole-step kernel is held to the registers of 6 waves per
- *                   SIMD; 40 KiB, 4
- *                   workgroups, otherwise); a tile of one PE may exceed it (up to
- *                   the 160 KiB of a compute unit).
+ *                   SIMD; 64 KiB for the FP32 forms of the Euler and reactive Euler
+ *                   WENO kernels, whose registers admit only 2-3 waves per SIMD;
+ *                   40 KiB, 4 workgroups, otherwise); a tile of one PE may exceed it
+ *                   (up to the 160 KiB of a compute unit).
  */
 typedef struct at_run_opts {
     int32_t tile_points, persistent, grid_per_cu, graph_steps;

@@ -30,7 +30,7 @@ import time
 from typing import Callable, Dict, List, Optional, Sequence
 
 # LDS budgets per tile tried in the first stage (0: the planner's default)
-BUDGETS_KIB = (0, 20, 22, 24, 26, 28, 32, 40, 64)
+BUDGETS_KIB = (0, 20, 22, 24, 26, 28, 32, 40, 64, 96, 128, 160)
 # launch shapes and orders tried in the second stage
 SHAPES = ({}, {"persistent": 1, "grid_per_cu": 4}, {"persistent": 1, "grid_per_cu": 6},
           {"persistent": 1, "grid_per_cu": 8}, {"xcd_remap": 1})
@@ -136,12 +136,13 @@ def autotune(problems: Sequence, steps: int = 100, graph_steps: int = 50,
 def main(argv=None):
     import at_workloads as W
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
-    ap.add_argument("--workload", default="c3", choices=["c3", "c5batch"])
+    ap.add_argument("--workload", default="c3", choices=["c3", "c4", "c5", "c5batch"])
     ap.add_argument("--precision", default="fp32c", choices=["fp32c", "fp32", "fp64"])
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--cache", default=None)
     args = ap.parse_args(argv)
-    base = W.batched_adr_c3() if args.workload == "c3" else W.detonation_batch_c5()
+    base = {"c3": W.batched_adr_c3, "c4": lambda: [W.euler_sod_c4()], "c5": lambda: [W.detonation_c5()],
+            "c5batch": W.detonation_batch_c5}[args.workload]()
     prs = [p.replace(precision=args.precision) for p in base]
     t0 = time.perf_counter()
     res = autotune(prs, steps=args.steps, cache=args.cache)

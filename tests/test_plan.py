@@ -78,3 +78,15 @@ def test_algorithmic_bytes_follow_the_layout(prec, make, S, H, F):
     assert e.query(Q_PES) == npes
     assert e.query(Q_STATE) == 2 * F * npts * s_state
     assert e.query(Q_STRIP) == 2 * npes * rec
+
+
+@pytest.mark.parametrize("prec,pes_per_tile", [("fp32c", 2), ("fp32", 2), ("fp64", 1)])
+def test_weno_default_budget_packs_two_pes_in_fp32(prec, pes_per_tile):
+    """The FP32 Euler WENO kernels default to 64 KiB per tile: a tile packs two of the
+    detonation's 256-point PEs (their registers admit only 2-3 waves per SIMD, so the
+    larger tile costs no occupancy); the FP64 form keeps one PE per tile (one PE already
+    exceeds its 40 KiB default, which a single-PE tile may)."""
+    pr = W.detonation_c5().replace(precision=prec)
+    e = _plan([pr])
+    assert e.query(Q_TILES) == pr.p // pes_per_tile
+    assert e.query(Q_LDS) <= (64 if prec != "fp64" else 160) * 1024
