@@ -159,6 +159,18 @@ int make_plan(const at_problem_desc* probs, int n_probs, const at_run_opts* opts
         const int kind = kind_of(d.pde, d.scheme);
         const bool f32 = d.precision != AT_FP64;
         pi.key = VariantKey{kind, halo_of(d.scheme), S, f32, ppt_small(kind, f32)};
+        {
+            // both tile classes of the combination must be compiled (e.g. the reactive
+            // Navier-Stokes kernels exist for the 4th- and 8th-order stencils only)
+            VariantKey kl = pi.key;
+            kl.ppt = ppt_large(kind, f32);
+            int64_t lds, rec;
+            if (!variant_sizes(pi.key, 1, 1, 1, &lds, &rec) || !variant_sizes(kl, 1, 1, 1, &lds, &rec)) {
+                err = fmt("problem %lld: no compiled kernel for pde %lld with scheme %lld", b, d.pde, d.scheme);
+                err += fmt(" and %lld RK stages", S);
+                return AT_EUNSUPPORTED;
+            }
+        }
         pi.F = fields_of(d.pde);
         pi.H = pi.key.H;
         pi.S = S;
@@ -167,7 +179,7 @@ int make_plan(const at_problem_desc* probs, int n_probs, const at_run_opts* opts
         pi.st_elems = (int64_t)pi.F * d.n;
         // the kernels address each array with 32-bit offsets: every array under 4 GiB
         if (pi.st_elems * (int64_t)MAXS * 8 >= ((int64_t)1 << 32)) {
-            err = fmt("problem %d: F x N = %lld state elements exceed the 32-bit offset range", b,
+            err = fmt("problem %lld: F x N = %lld state elements exceed the 32-bit offset range", b,
                       (long long)pi.st_elems);
             return AT_EUNSUPPORTED;
         }
@@ -221,8 +233,8 @@ int make_plan(const at_problem_desc* probs, int n_probs, const at_run_opts* opts
             bool fits = cur.npe > 0 && cur.npts + np <= pack;
             if (fits) {
                 int64_t lds, rec;
-                variant_sizes(ks, (int)(cur.npts + np), cur.npe + 1, pi.J, &lds, &rec);
-                fits = lds <= lds_budget;
+                fits = variant_sizes(ks, (int)(cur.npts + np), cur.npe + 1, pi.J, &lds, &rec) &&
+                       lds <= lds_budget;
             }
             if (!fits && cur.npe > 0) {
                 small[b].push_back(cur);
@@ -239,7 +251,10 @@ int make_plan(const at_problem_desc* probs, int n_probs, const at_run_opts* opts
         for (int cls = 0; cls < 2; ++cls)
             for (const Tile& t : (cls ? large[b] : small[b])) {
                 int64_t lds, rec;
-                variant_sizes(cls ? kl : ks, t.npts, t.npe, pi.J, &lds, &rec);
+                if (!variant_sizes(cls ? kl : ks, t.npts, t.npe, pi.J, &lds, &rec)) {
+                    err = fmt("problem %lld: kernel variant not compiled", b);
+                    return AT_EUNSUPPORTED;
+                }
                 if (lds > lds_hard) {
                     err = fmt("problem %lld: tile needs %lld bytes of LDS", b, lds);
                     return AT_EUNSUPPORTED;
@@ -297,7 +312,10 @@ int make_plan(const at_problem_desc* probs, int n_probs, const at_run_opts* opts
             g.npts_max = std::max(g.npts_max, t.npts);
             g.npe_max = std::max(g.npe_max, t.npe);
             int64_t lds, rec;
-            variant_sizes(g.key, t.npts, t.npe, g.jmax, &lds, &rec);   // layouts are per tile
+            if (!variant_sizes(g.key, t.npts, t.npe, g.jmax, &lds, &rec)) {   // layouts are per tile
+                err = "kernel variant not compiled";
+                return AT_EUNSUPPORTED;
+            }
             g.lds_bytes = std::max(g.lds_bytes, lds);
         }
         plan.tiles_bt.insert(plan.tiles_bt.end(), ts.begin(), ts.end());
@@ -328,10 +346,13 @@ int make_plan(const at_problem_desc* probs, int n_probs, const at_run_opts* opts
             if (d.precision == AT_FP32C) o = align256(o + 4 * (size_t)pi.st_elems);
         }
         int64_t lds;
-        variant_sizes(pi.key, 1, 1, 1, &lds, &pi.rec_bytes);
+        if (!variant_sizes(pi.key, 1, 1, 1, &lds, &pi.rec_bytes)) {
+            err = fmt("problem %lld: kernel variant not compiled", b);
+            return AT_EUNSUPPORTED;
+        }
         pi.ring_bytes = (int64_t)pi.D * d.p * 2 * pi.rec_bytes;
         if (pi.ring_bytes >= ((int64_t)1 << 32)) {
-            err = fmt("problem %d: strip ring of %lld bytes exceeds the 32-bit offset range", b,
+            err = fmt("problem %lld: strip ring of %lld bytes exceeds the 32-bit offset range", b,
                       (long long)pi.ring_bytes);
             return AT_EUNSUPPORTED;
         }

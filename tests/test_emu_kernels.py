@@ -129,3 +129,19 @@ def test_emu_domains_shorter_than_a_window(prec, n, p):
     e = at_emu.Emu([pr])
     e.step(10)
     assert norm_err(pr, e.state(0), _oracle(pr, 10).state()) < tol(prec)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32c"])
+@pytest.mark.parametrize("make", [lambda: W.euler_sod_c4(n=2048, p=8),
+                                  lambda: W.detonation_c5(n=2048, p=8, precision="fp64")])
+def test_emu_multi_pe_weno_tiles(prec, make):
+    """WENO tiles of several PEs (forced by the tile size and LDS budget) give the result
+    of one PE per tile bit for bit, and the oracle's."""
+    pr = with_precision(make(), prec)
+    one = at_emu.Emu([pr], tile_points=256)
+    many = at_emu.Emu([pr], tile_points=1024, lds_budget=160 * 1024)
+    assert one.query(1) == pr.p and many.query(1) < pr.p
+    one.step(12)
+    many.step(12)
+    assert np.array_equal(one.state(0), many.state(0))
+    assert norm_err(pr, many.state(0), _oracle(pr, 12).state()) < tol(prec, pr)

@@ -90,3 +90,13 @@ def test_weno_default_budget_packs_two_pes_in_fp32(prec, pes_per_tile):
     e = _plan([pr])
     assert e.query(Q_TILES) == pr.p // pes_per_tile
     assert e.query(Q_LDS) <= (64 if prec != "fp64" else 160) * 1024
+
+
+def test_uncompiled_combination_rejected():
+    """A pde / scheme combination that validates but has no compiled kernel (the reactive
+    Navier-Stokes kernels exist for the 4th- and 8th-order stencils only) is refused with
+    a clear message instead of a plan built from unset sizes."""
+    pr = W.reactive_ns_c2(n=512, p=8).replace(scheme="fd2")
+    with pytest.raises(at_emu.EmuError) as ei:
+        _plan([pr])
+    assert "-2" in str(ei.value) and "no compiled kernel" in str(ei.value)
