@@ -138,7 +138,7 @@ int at_init(const at_problem_desc* probs, int n_probs, const at_run_opts* opts, 
  * aligned) and the HIP stream (hipStream_t, NULL = default stream) on the
  * current device.  Uploads the problem tables (stream-ordered) and creates the
  * side streams and events of at_batch_step (one per kernel variant after the
- * first).  Errors: AT_EINVAL, AT_EHIP. */
+ * first).  Binding forgets all progress (as at_reset).  Errors: AT_EINVAL, AT_EHIP. */
 int at_bind(at_ctx* ctx, void* d_workspace, size_t bytes, void* hip_stream);
 
 /* Set problem `prob`'s level-0 state: F x N doubles (structure of arrays,

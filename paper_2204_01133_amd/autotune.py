@@ -39,9 +39,13 @@ _SIG_FIELDS = ("pde", "scheme", "mode", "rk", "precision", "n", "p", "kmax", "at
 
 
 def signature(problems: Sequence, device_name: str = "") -> str:
-    """Hash of what decides the plan and the kernels of a workload."""
+    """Hash of what decides the plan and the kernels of a workload: the problems, the
+    device and the library's sources (a cached choice goes stale when the planner or
+    the kernels change)."""
+    from .build import source_hash
     rows = [[getattr(p, f) for f in _SIG_FIELDS] + [len(getattr(p, "cdf", ()) or ())] for p in problems]
-    blob = json.dumps({"device": device_name, "problems": rows}, sort_keys=True).encode()
+    blob = json.dumps({"device": device_name, "problems": rows, "sources": source_hash()},
+                      sort_keys=True).encode()
     return hashlib.sha256(blob).hexdigest()[:24]
 
 

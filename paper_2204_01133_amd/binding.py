@@ -103,6 +103,16 @@ def load_library():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"libat.so not built ({LIB_PATH}); run python -m paper_2204_01133_amd.build")
+    from . import build as _build
+    try:
+        with open(_build.STAMP) as fh:
+            stamp = fh.read().strip()
+    except OSError:
+        stamp = None
+    if stamp != _build.source_hash():
+        raise RuntimeError(f"libat.so ({LIB_PATH}) was not built from the current sources "
+                           f"(stamp {stamp}, sources {_build.source_hash()}); rebuild with "
+                           "python -m paper_2204_01133_amd.build")
     L = ctypes.CDLL(LIB_PATH)
     P = ctypes.POINTER
     vp = ctypes.c_void_p
@@ -164,6 +174,10 @@ class ATSolver:
             self.workspace_bytes = int(nbytes.value)
             self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
             self.ws = torch.empty(self.workspace_bytes + 256, dtype=torch.uint8, device=self.device)
+            # the workspace is used on the solver's stream: its memory is not handed to
+            # another tensor before that stream's pending work is done
+            if self.stream != torch.cuda.current_stream(self.device):
+                self.ws.record_stream(self.stream)
             base = self.ws.data_ptr()
             self._ws_ptr = (base + 255) & ~255
             self._check(self.L.at_bind(self._h, ctypes.c_void_p(self._ws_ptr), self.workspace_bytes,
@@ -181,6 +195,7 @@ class ATSolver:
 
     def close(self):
         if getattr(self, "_h", None):
+            self.L.at_sync(self._h)             # no launch in flight on the workspace
             self.L.at_free(self._h)
             self._h = None
 
@@ -194,9 +209,17 @@ class ATSolver:
     def set_state(self, b: int, q):
         torch = self.torch
         if isinstance(q, torch.Tensor) and q.is_cuda:
+            # q (and its converted copy) are written on the caller's current stream and
+            # read by the library on the solver's stream: order the two, and keep their
+            # memory from being reused before the solver's stream has read it
+            cur = torch.cuda.current_stream(self.device)
             t = q.to(dtype=torch.float64).contiguous()
+            if self.stream != cur:
+                self.stream.wait_stream(cur)
             self._check(self.L.at_set_state(self._h, b, ctypes.c_void_p(t.data_ptr()), 1))
-            self._keep = t
+            if self.stream != cur:
+                t.record_stream(self.stream)
+                q.record_stream(self.stream)
         else:
             a = np.ascontiguousarray(q, dtype=np.float64)
             self._check(self.L.at_set_state(self._h, b, a.ctypes.data_as(ctypes.c_void_p), 0))
@@ -223,9 +246,18 @@ class ATSolver:
         return out
 
     def state_device(self, b: int):
+        """The state as a device tensor, ready for work on the caller's current stream
+        (which is made to wait for the solver's stream)."""
+        torch = self.torch
         pr = self.problems[b]
-        out = self.torch.empty((pr.nf, pr.n), dtype=self.torch.float64, device=self.device)
+        cur = torch.cuda.current_stream(self.device)
+        out = torch.empty((pr.nf, pr.n), dtype=torch.float64, device=self.device)
+        if self.stream != cur:
+            self.stream.wait_stream(cur)        # out's memory is free on the solver's stream too
         self._check(self.L.at_get_state(self._h, b, ctypes.c_void_p(out.data_ptr()), 1))
+        if self.stream != cur:
+            out.record_stream(self.stream)
+            cur.wait_stream(self.stream)
         return out
 
     def delays(self, b: int, step0: int, n_steps: int) -> Tuple[np.ndarray, np.ndarray]:

@@ -10,6 +10,7 @@ libat_emu.so: the same tile code compiled for the host with bounds checks
 from __future__ import annotations
 
 import concurrent.futures as cf
+import hashlib
 import os
 import shutil
 import subprocess
@@ -25,7 +26,28 @@ HIP_SOURCES = ["at_api.hip", "at_k_adr.hip", "at_k_adr32.hip", "at_k_rns.hip", "
                "at_k_reul.hip"]
 HOST_SOURCES = ["at_plan.cpp"]
 
+STAMP = os.path.join(BUILD, "libat.stamp")
+INCLUDE = os.path.join(os.path.dirname(HERE), "include")
+
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")
+
+
+def source_files():
+    """Every source libat.so is built from (kernels, planner, C ABI header)."""
+    files = sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC)
+                   if f.endswith((".hip", ".hpp", ".cpp", ".h")))
+    return files + [os.path.join(INCLUDE, "at.h")]
+
+
+def source_hash() -> str:
+    """SHA-256 (first 16 hex digits) of the sources, written beside the library when it
+    is built and compared when it is loaded, so that a stale build is refused."""
+    h = hashlib.sha256()
+    for f in source_files():
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 HIP_FLAGS = ["-std=c++17", "-O3", "--offload-arch=gfx950", "-fPIC", "-ffp-contract=on",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wno-unused-result"]
 
@@ -40,6 +62,7 @@ def _run(cmd):
 
 def build_lib(jobs: int = 8) -> str:
     os.makedirs(BUILD, exist_ok=True)
+    stamp = source_hash()
     objs, cmds = [], []
     for src in HIP_SOURCES + HOST_SOURCES:
         obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
@@ -51,6 +74,9 @@ def build_lib(jobs: int = 8) -> str:
     tmp = LIB + f".tmp{os.getpid()}"
     _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs)
     os.replace(tmp, LIB)
+    with open(STAMP + ".tmp", "w") as fh:
+        fh.write(stamp + "\n")
+    os.replace(STAMP + ".tmp", STAMP)
     return LIB
 
 

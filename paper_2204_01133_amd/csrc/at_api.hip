@@ -118,9 +118,14 @@ int upload_probs(at_ctx* c) {
     return AT_OK;
 }
 
+int check_bound(at_ctx* c) {
+    if (!c->bound) return fail(c, AT_ESTATE, "workspace not bound");
+    return AT_OK;
+}
+
 int check_ready(at_ctx* c) {
     if (!c) return AT_EINVAL;
-    if (!c->bound) return fail(c, AT_ESTATE, "workspace not bound");
+    if (int rb = check_bound(c)) return rb;
     for (size_t b = 0; b < c->state_set.size(); ++b)
         if (!c->state_set[b]) return fail(c, AT_ESTATE, "state of a problem not set");
     return AT_OK;
@@ -154,7 +159,8 @@ void free_side_streams(at_ctx* c) {
 // and their own ring records of level n), so the groups run concurrently.
 int batched_step_launches(at_ctx* c, const int64_t* step_ptr, int64_t step_off) {
     const size_t ng = c->plan.groups.size();
-    if (ng > 1) {
+    const bool concurrent = ng > 1;
+    if (concurrent) {
         if (c->side.size() + 1 < ng || c->ev.size() < ng) return fail(c, AT_ESTATE, "side streams missing");
         HIPCHK(c, hipEventRecord(c->ev[0], c->stream));
         for (size_t i = 1; i < ng; ++i) HIPCHK(c, hipStreamWaitEvent(c->side[i - 1], c->ev[0], 0));
@@ -175,10 +181,10 @@ int batched_step_launches(at_ctx* c, const int64_t* step_ptr, int64_t step_off) 
         const int persistent = c->plan.opts.persistent == 1 ? 1 : 0;
         const int per_cu = c->plan.opts.grid_per_cu > 0 ? c->plan.opts.grid_per_cu : 6;
         const int grid = persistent ? std::min(g.ntiles, per_cu * c->num_cus) : g.ntiles;
-        int rc = launch_key(c, g.key, a, grid, gi == 0 ? c->stream : c->side[gi - 1]);
+        int rc = launch_key(c, g.key, a, grid, (gi == 0 || !concurrent) ? c->stream : c->side[gi - 1]);
         if (rc) return rc;
     }
-    for (size_t i = 1; i < ng; ++i) {
+    for (size_t i = 1; concurrent && i < ng; ++i) {
         HIPCHK(c, hipEventRecord(c->ev[i], c->side[i - 1]));
         HIPCHK(c, hipStreamWaitEvent(c->stream, c->ev[i], 0));
     }
@@ -252,6 +258,9 @@ int at_bind(at_ctx* c, void* d_workspace, size_t bytes, void* hip_stream) {
     if (bytes < c->plan.total) return fail(c, AT_EINVAL, "workspace too small");
     if (((uintptr_t)d_workspace & 255) != 0) return fail(c, AT_EINVAL, "workspace not 256-byte aligned");
     drop_graph(c);
+    c->step = 0;
+    c->stage = 0;
+    std::fill(c->state_set.begin(), c->state_set.end(), 0);
     c->ws = (unsigned char*)d_workspace;
     c->ws_bytes = bytes;
     c->stream = (hipStream_t)hip_stream;
@@ -275,7 +284,7 @@ int at_reset(at_ctx* c) {
 
 int at_set_state(at_ctx* c, int prob, const double* q, int q_on_device) {
     if (!c || !q) return AT_EINVAL;
-    if (!c->bound) return fail(c, AT_ESTATE, "workspace not bound");
+    if (int rb = check_bound(c)) return rb;
     if (prob < 0 || prob >= (int)c->plan.desc.size()) return fail(c, AT_EINVAL, "problem index");
     if (c->step != 0 || c->stage != 0) return fail(c, AT_ESTATE, "state set after stepping (at_reset first)");
     const ProbInfo& pi = c->plan.info[prob];
@@ -395,7 +404,7 @@ int at_rk_stage(at_ctx* c, int stage) {
 
 int at_get_state(at_ctx* c, int prob, double* out, int out_on_device) {
     if (!c || !out) return AT_EINVAL;
-    if (!c->bound) return fail(c, AT_ESTATE, "workspace not bound");
+    if (int rb = check_bound(c)) return rb;
     if (prob < 0 || prob >= (int)c->plan.desc.size()) return fail(c, AT_EINVAL, "problem index");
     const ProbInfo& pi = c->plan.info[prob];
     const int prec = c->plan.desc[prob].precision;
@@ -425,7 +434,7 @@ int at_get_state(at_ctx* c, int prob, double* out, int out_on_device) {
 
 int at_get_delays(at_ctx* c, int prob, int64_t step0, int n_steps, uint8_t* drawn, uint8_t* eff) {
     if (!c || !drawn || !eff) return AT_EINVAL;
-    if (!c->bound) return fail(c, AT_ESTATE, "workspace not bound");
+    if (int rb = check_bound(c)) return rb;
     if (prob < 0 || prob >= (int)c->plan.desc.size()) return fail(c, AT_EINVAL, "problem index");
     const int64_t cap = c->plan.opts.log_steps;
     if (cap == 0) return fail(c, AT_EINVAL, "delay log disabled (log_steps = 0)");
@@ -446,7 +455,7 @@ int at_get_delays(at_ctx* c, int prob, int64_t step0, int n_steps, uint8_t* draw
 
 int at_set_delay_override(at_ctx* c, int prob, const uint8_t* sched, int64_t step0, int n_steps) {
     if (!c) return AT_EINVAL;
-    if (!c->bound) return fail(c, AT_ESTATE, "workspace not bound");
+    if (int rb = check_bound(c)) return rb;
     if (prob < 0 || prob >= (int)c->plan.desc.size()) return fail(c, AT_EINVAL, "problem index");
     if (n_steps < 0 || step0 < 0) return fail(c, AT_EINVAL, "negative step");
     if (n_steps > c->plan.opts.override_steps) return fail(c, AT_EINVAL, "schedule longer than override_steps");
