@@ -74,29 +74,34 @@ def build(force: bool = False) -> str:
 def lib():
     global _lib
     if _lib is None:
-        path = build()
-        L = ctypes.CDLL(path)
-        P = ctypes.POINTER
-        L.orc_create.argtypes = [P(OrcProblem), P(ctypes.c_double), P(ctypes.c_void_p)]
-        L.orc_free.argtypes = [ctypes.c_void_p]
-        L.orc_free.restype = None
-        L.orc_set_history.argtypes = [ctypes.c_void_p, ctypes.c_int, P(ctypes.c_double), ctypes.c_int64]
-        L.orc_step.argtypes = [ctypes.c_void_p, ctypes.c_int]
-        L.orc_current_step.argtypes = [ctypes.c_void_p]
-        L.orc_current_step.restype = ctypes.c_int64
-        L.orc_get_state.argtypes = [ctypes.c_void_p, P(ctypes.c_double)]
-        L.orc_get_stage_level.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, P(ctypes.c_double)]
-        L.orc_get_delays.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, P(ctypes.c_uint8),
-                                     P(ctypes.c_uint8)]
-        L.orc_set_override.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, P(ctypes.c_uint8)]
-        L.orc_get_fluxes.argtypes = [ctypes.c_void_p, ctypes.c_int, P(ctypes.c_double)]
-        L.orc_mix64.argtypes = [ctypes.c_uint64]
-        L.orc_mix64.restype = ctypes.c_uint64
-        L.orc_draw.argtypes = [P(OrcProblem), ctypes.c_int64, ctypes.c_int64, ctypes.c_int]
-        L.orc_extrap_weights.argtypes = [ctypes.c_int, ctypes.c_int, P(ctypes.c_double)]
-        L.orc_rhs_sync.argtypes = [P(OrcProblem), P(ctypes.c_double), P(ctypes.c_double)]
-        _lib = L
+        _lib = load(build())
     return _lib
+
+
+def load(path: str):
+    """Load an oracle library built from at_oracle.c (the tests also load copies of
+    it with a planted mistake, to show that a pin catches that mistake)."""
+    L = ctypes.CDLL(path)
+    P = ctypes.POINTER
+    L.orc_create.argtypes = [P(OrcProblem), P(ctypes.c_double), P(ctypes.c_void_p)]
+    L.orc_free.argtypes = [ctypes.c_void_p]
+    L.orc_free.restype = None
+    L.orc_set_history.argtypes = [ctypes.c_void_p, ctypes.c_int, P(ctypes.c_double), ctypes.c_int64]
+    L.orc_step.argtypes = [ctypes.c_void_p, ctypes.c_int]
+    L.orc_current_step.argtypes = [ctypes.c_void_p]
+    L.orc_current_step.restype = ctypes.c_int64
+    L.orc_get_state.argtypes = [ctypes.c_void_p, P(ctypes.c_double)]
+    L.orc_get_stage_level.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, P(ctypes.c_double)]
+    L.orc_get_delays.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, P(ctypes.c_uint8),
+                                 P(ctypes.c_uint8)]
+    L.orc_set_override.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, P(ctypes.c_uint8)]
+    L.orc_get_fluxes.argtypes = [ctypes.c_void_p, ctypes.c_int, P(ctypes.c_double)]
+    L.orc_mix64.argtypes = [ctypes.c_uint64]
+    L.orc_mix64.restype = ctypes.c_uint64
+    L.orc_draw.argtypes = [P(OrcProblem), ctypes.c_int64, ctypes.c_int64, ctypes.c_int]
+    L.orc_extrap_weights.argtypes = [ctypes.c_int, ctypes.c_int, P(ctypes.c_double)]
+    L.orc_rhs_sync.argtypes = [P(OrcProblem), P(ctypes.c_double), P(ctypes.c_double)]
+    return L
 
 
 def _dptr(a: np.ndarray):

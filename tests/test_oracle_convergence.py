@@ -34,11 +34,13 @@ def order(e):
 # --------------------------------------------------------------------------
 # advection-diffusion
 # --------------------------------------------------------------------------
-def _adv_diff_err(n, mode, kmax=2, c=1.0, alpha=0.02, C=10.0, t_end=0.1, p=8, seed=1):
+def _adv_diff_err(n, mode, kmax=2, c=1.0, alpha=0.02, C=10.0, t_end=0.1, p=8, seed=1, scheme="fd4",
+                  levels=0):
     dx = 1.0 / n
     steps = int(math.ceil(t_end / (C * dx * dx)))
-    pr = W.adv_diff_c1(n=n, p=p, kmax=kmax, mode=mode, c=c, alpha=alpha, steps=steps, seed=seed)
-    pr = pr.replace(dt=t_end / steps)
+    pr = W.adv_diff_c1(n=n, p=p, kmax=kmax, mode=mode, c=c, alpha=alpha, steps=steps, seed=seed,
+                       scheme=scheme)
+    pr = pr.replace(dt=t_end / steps, at_levels=levels)
     u = oracle.run(pr)[0]
     return np.abs(u - W.adv_diff_exact(pr.x(), t_end, c, alpha)).max()
 
@@ -51,6 +53,34 @@ def test_adv_diff_orders():
     assert (o_at > 3.3).all(), es
     assert (o_as < 2.0).all() and (o_as > 0.5).all(), es
     assert es["as"][-1] > 30 * es["at"][-1]
+
+
+def test_fd8_with_three_level_at_halo_orders():
+    """The 8th-order interior with the 3-level AT halo (the same Lagrange family as
+    Table A) on the exact advection-diffusion solution, dt = C dx^2, random delays
+    uniform on {0..2}.  SYNC converges at 8th order (the interior stencil); AT at the
+    order of the halo's time extrapolation, O(dt^3 / dx^2) = O(dx^4) locally at O(1)
+    points (observed 4.6-5.3); AS, the standard stencil on the delayed level, at first
+    order.  A wrong FD8 weight drops SYNC to 2nd order or below; a wrong extrapolation
+    weight drops AT to the AS order."""
+    ns = [32, 64, 128, 256]
+    es = {m: [_adv_diff_err(n, m, scheme="fd8") for n in ns] for m in ("sync", "at", "as")}
+    o_sync, o_at, o_as = order(es["sync"]), order(es["at"]), order(es["as"])
+    assert (o_sync > 7.5).all(), es
+    assert (o_at > 4.0).all(), es
+    assert (o_as < 1.5).all() and (o_as > 0.5).all(), es
+    assert es["as"][-1] > 1e4 * es["at"][-1]
+
+
+def test_fd8_extrapolation_level_choice():
+    """Why the FD8 interior takes 3 extrapolation levels: at the time step of the order
+    sweep above (diffusion number alpha dt / dx^2 = 0.2) the order-matched 5 levels grow
+    without bound under delays of up to 2 steps, while 3 levels converge; 5 levels need
+    a step about ten times smaller (diffusion number 0.02)."""
+    blow = _adv_diff_err(128, "at", scheme="fd8", levels=5)
+    assert not np.isfinite(blow) or blow > 1e3
+    assert _adv_diff_err(128, "at", scheme="fd8", levels=3) < 1e-4
+    assert _adv_diff_err(128, "at", scheme="fd8", levels=5, C=1.0) < 1e-8
 
 
 def test_rkat1_leading_delay_term():
