@@ -11,7 +11,7 @@ import pytest
 
 import at_workloads as W
 import oracle
-from cases import batch_case, norm_err, single_cases, tol, with_precision
+from cases import batch_case, field_scale, norm_err, single_cases, tol, with_precision
 
 pytestmark = pytest.mark.gpu
 
@@ -247,55 +247,91 @@ def test_full_c3_sampled(torch, prec):
         assert np.isfinite(u).all() and u.min() > -0.2 and u.max() < 1.3
 
 
-def test_full_c4_first_steps(torch):
-    pr = W.euler_sod_c4()
-    s = solver([pr])
-    s.batch_step(10)
-    assert norm_err(pr, s.state(0), _oracle(pr, 10).state()) < 1e-12
+# the oracle states of the full-length configurations, computed in worker processes on
+# the host's cores from the start of this module (see tests/oracle_jobs.py)
+@pytest.fixture(scope="module", autouse=True)
+def full_refs(request):
+    """Started with the module's first test when any full-length test is selected."""
+    if not any(it.name.startswith("test_full_c") and it.module is request.module
+               for it in request.session.items):
+        yield None
+        return
+    import oracle_jobs
+    refs = oracle_jobs.Refs()
+    yield refs
+    refs.close()
 
 
-def test_full_c5_first_steps(torch):
-    pr = W.detonation_c5()
-    s = solver([pr])
-    s.batch_step(5)
-    assert norm_err(pr, s.state(0), _oracle(pr, 5).state()) < tol("fp32c")
+def _field_report(name, prec, pr, got, ref):
+    errs = np.abs(got - ref).max(axis=1) / field_scale(pr, ref)
+    print(f"{name} {prec} N {pr.n}: per-field error " + " ".join(f"{e:.2e}" for e in errs), flush=True)
+    return errs
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32c"])
-def test_full_c2_first_steps(torch, prec):
-    """The reactive NS flame at its full size (N 8192, P 64, FD8 with the 3-level halo,
-    four fields, one-step Arrhenius chemistry): state and delay logs of 20 steps."""
-    pr = with_precision(W.reactive_ns_c2(), prec)
-    steps = 20
-    s = solver([pr], log_steps=steps + 1)
+def test_full_c4(torch, full_refs, prec):
+    """The Euler shock tube at its full size and length (N 65,536, P 256, AT-WENO5 with
+    delays up to 4, SSP-RK3, 200 steps) in the launch form of its timing (batched, graphs
+    of 50 steps), per field against the oracle."""
+    import oracle_jobs
+    pr, steps = oracle_jobs.full_length_cases()["c4"]
+    pr = with_precision(pr, prec)
+    s = solver([pr], graph_steps=50)
     s.batch_step(steps)
-    o = _oracle(pr, steps)
-    assert norm_err(pr, s.state(0), o.state()) < tol(prec)
-    d1, e1 = s.delays(0, 0, steps)
-    d2, e2 = o.delays(0, steps)
-    assert np.array_equal(d1, d2) and np.array_equal(e1, e2)
+    errs = _field_report("c4", prec, pr, s.state(0), full_refs.get("c4"))
+    assert (errs < tol(prec, pr)).all(), errs
 
 
-_C5B_REF = {}
+@pytest.mark.parametrize("prec", ["fp64", "fp32c"])
+def test_full_c2(torch, full_refs, prec):
+    """The reactive NS flame at its full size and length (N 8192, P 64, FD8 with the
+    3-level halo, delays up to 4, RK4, 2000 steps), graphs of 50 steps; delay logs of
+    the last 64 steps bit-exact."""
+    import oracle_jobs
+    pr, steps = oracle_jobs.full_length_cases()["c2"]
+    pr = with_precision(pr, prec)
+    s = solver([pr], graph_steps=50, log_steps=64)
+    s.batch_step(steps)
+    errs = _field_report("c2", prec, pr, s.state(0), full_refs.get("c2"))
+    assert (errs < tol(prec, pr)).all(), errs
+    # the delays of the last 64 steps against the oracle's generator (one draw per PE and
+    # step, both sides); this late every delay is used as drawn
+    d, e = s.delays(0, steps - 64, 64)
+    want = np.array([[[oracle.draw(pr, n, k, 0)] * 2 for k in range(pr.p)]
+                     for n in range(steps - 64, steps)], dtype=np.uint8)
+    assert np.array_equal(d, want) and np.array_equal(e, want)
 
 
 @pytest.mark.parametrize("prec", ["fp32c", "fp64"])
-def test_full_c5_batch_sampled(torch, prec):
-    """The 256-tube detonation batch (19.2 M points) in the launch configuration of its
-    timing: one launch per step, replayed from a graph of 50 steps.  The smallest and the
-    largest tube against the oracle after those 50 steps (the FP32 form within its bound for
-    the reacting front); every tube finite with positive density."""
-    prs = [p.replace(precision=prec) for p in W.detonation_batch_c5()]
-    steps = 50
-    s = solver(prs, graph_steps=steps, log_steps=4)
+def test_full_c5_single(torch, full_refs, prec):
+    """The 2^20-point detonation (P 4096) in its launch form, as far as the serial oracle
+    goes in the time of a test (20 steps)."""
+    import oracle_jobs
+    pr, steps = oracle_jobs.full_length_cases()["c5"]
+    pr = with_precision(pr, prec)
+    s = solver([pr], graph_steps=steps)
     s.batch_step(steps)
-    ns = np.array([p.n for p in prs])
-    for b in sorted({int(ns.argmin()), int(ns.argmax())}):
-        if b not in _C5B_REF:
-            _C5B_REF[b] = _oracle(prs[b], steps).state()
-        err = norm_err(prs[b], s.state(b), _C5B_REF[b])
-        print(f"tube {b} N {prs[b].n} {prec}: {err:.3e}", flush=True)
-        assert err < tol(prec, prs[b]), b
+    errs = _field_report("c5", prec, pr, s.state(0), full_refs.get("c5"))
+    assert (errs < tol(prec, pr)).all(), errs
+
+
+@pytest.mark.parametrize("prec", ["fp32c", "fp64"])
+def test_full_c5_batch(torch, full_refs, prec):
+    """The 256-tube detonation batch (19.2 M points) at its full length (200 steps) in the
+    launch configuration of its timing: one launch per step, graphs of 50 steps.  The
+    smallest and the largest tube per field against the oracle (the FP32 form within its
+    bound for the reacting front); every tube finite with positive density."""
+    import oracle_jobs
+    cases = oracle_jobs.full_length_cases()
+    prs = [p.replace(precision=prec) for p in W.detonation_batch_c5()]
+    steps = cases["c5batch_min"][1]
+    s = solver(prs, graph_steps=50, log_steps=4)
+    s.batch_step(steps)
+    for key in ("c5batch_min", "c5batch_max"):
+        b = cases[key][0].problem_id
+        assert prs[b].n == cases[key][0].n
+        errs = _field_report(key, prec, prs[b], s.state(b), full_refs.get(key))
+        assert (errs < tol(prec, prs[b])).all(), (key, errs)
     for b in range(0, len(prs), 15):
         u = s.state(b)
         assert np.isfinite(u).all() and u[0].min() > 0.0, b
