@@ -14,7 +14,7 @@ per problem) on the same data, with the error of each batched form against the
 FP64 oracle on sampled problems.
 
     python bench.py [--gpus 1] [--steps 1000] [--warmup 20]
-    python bench.py --config {c1,c2,c4,c5,c5batch} --steps 100   # other configurations, timing only
+    python bench.py --config {c1,c2,c4,c5,c5batch} --steps 100   # other configurations
 """
 from __future__ import annotations
 
@@ -73,20 +73,33 @@ def algorithmic_bytes_per_step(prs, solver) -> dict:
             "total": state + strip_w + strip_r}
 
 
-def warmup_steps(warmup, steps, graph_steps=50):
+GRAPH_STEPS = 50
+
+
+def graph_len(steps, graph_steps=GRAPH_STEPS):
+    """Steps per captured graph for a timed run of `steps`: at most GRAPH_STEPS, and no
+    more than the run, so that every timed step is replayed from a graph."""
+    return max(1, min(graph_steps, steps)) if graph_steps > 0 else 0
+
+
+def warmup_steps(warmup, steps, graph_steps=GRAPH_STEPS):
     """Untimed steps before the timed ones: at least one graph's worth when the timed
     steps replay a graph, so that capturing and instantiating it is not timed."""
-    return max(warmup, graph_steps) if 0 < graph_steps <= steps else warmup
+    g = graph_len(steps, graph_steps)
+    return max(warmup, g) if g > 0 else warmup
 
 
-def time_form(prs, steps, warmup, method="batch_step", graph_steps=50, **opts):
+def time_form(prs, steps, warmup, method="batch_step", graph_steps=GRAPH_STEPS, **opts):
+    """Seconds for `steps` steps (HIP events on the stream the tile kernels are launched
+    on), after the untimed warm-up; returns (solver, seconds, wall seconds, graph length)."""
     import torch
     from paper_2204_01133_amd import ATSolver
+    g = graph_len(steps, graph_steps) if method == "batch_step" else 0
     st = torch.cuda.Stream()
     with torch.cuda.stream(st):
-        s = ATSolver(prs, stream=st, graph_steps=graph_steps, **opts)
+        s = ATSolver(prs, stream=st, graph_steps=g, **opts)
         run = getattr(s, method)
-        run(warmup_steps(warmup, steps, graph_steps) if method == "batch_step" else warmup)
+        run(warmup_steps(warmup, steps, g) if method == "batch_step" else warmup)
         torch.cuda.synchronize()
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
@@ -97,35 +110,78 @@ def time_form(prs, steps, warmup, method="batch_step", graph_steps=50, **opts):
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         ms = e0.elapsed_time(e1)
-    return s, ms / 1000.0, wall
+    return s, ms / 1000.0, wall, g
 
 
 def _oracle_job(args):
-    pr, steps = args
+    """One sampled problem on the oracle: its state after `keep` steps (for the errors of
+    the GPU forms) and the CPU seconds of all `steps` steps (creation not included)."""
+    pr, keep, steps = args
     import oracle
-    t = time.perf_counter()
     with oracle.Oracle(pr.replace(precision="fp64")) as o:
-        o.step(steps)
+        t = time.perf_counter()
+        o.step(keep)
         out = o.state()
-    return out, time.perf_counter() - t
+        if steps > keep:
+            o.step(steps - keep)
+        return out, time.perf_counter() - t
 
 
-def oracle_sample(prs, idx, steps, workers):
+def _noop(_):
+    return os.getpid()
+
+
+def host_info():
+    """Host CPU as seen by this process: logical CPUs, the ones it may run on, model."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        allowed = len(os.sched_getaffinity(0))
+    except Exception:
+        allowed = os.cpu_count()
+    return {"nproc": os.cpu_count(), "affinity": allowed, "model": model}
+
+
+def oracle_sample(prs, idx, keep, steps, workers):
+    """Run the sampled problems on the oracle in `workers` processes.  The pool is
+    started and every worker has run a no-op before the clock starts, so the timed
+    region is the oracle's own stepping (and the return of the states)."""
     import multiprocessing as mp
-    jobs = [(prs[i], steps) for i in idx]
-    t0 = time.perf_counter()
+    jobs = [(prs[i], keep, steps) for i in idx]
     if workers > 1:
         ctx = mp.get_context("fork")
         with ctx.Pool(workers) as pool:
-            res = pool.map(_oracle_job, jobs)
+            pool.map(_noop, range(4 * workers), chunksize=1)
+            t0 = time.perf_counter()
+            res = pool.map(_oracle_job, jobs, chunksize=1)
+            wall = time.perf_counter() - t0
     else:
+        t0 = time.perf_counter()
         res = [_oracle_job(j) for j in jobs]
-    wall = time.perf_counter() - t0
+        wall = time.perf_counter() - t0
     return [r[0] for r in res], wall, sum(r[1] for r in res)
 
 
 def norm_err(got, ref):
     return float(np.abs(got - ref).max() / np.abs(ref).max())
+
+
+def field_errs(pr, got, ref):
+    """Norm-wise relative error per field: max |got - ref| / scale of the field (max |ref|;
+    for the momentum of the gas-dynamics problems, which is near zero at rest, at least
+    max(rho) times the wave-speed scale sqrt(max E / max rho))."""
+    sc = np.abs(ref).max(axis=1).astype(float)
+    if pr.pde in ("euler", "reactive_euler", "reactive_ns"):
+        rho = np.abs(ref[0]).max()
+        sc[1] = max(sc[1], rho * np.sqrt(max(np.abs(ref[2]).max() / max(rho, 1e-300), 1e-300)))
+    return (np.abs(got - ref).max(axis=1) / np.maximum(sc, 1e-300)).tolist()
 
 
 # the other configurations (parity cases of the tests): timed here for the record, not
@@ -141,27 +197,87 @@ OTHER_CONFIGS = {
 }
 
 
-def run_other(name, steps, warmup):
+# Algorithmic FLOPs per own point and RK stage of the WENO kinds, counted from the
+# method's formulas (a division, square root or exp counts as one; the synchronous
+# stages recomputed on the boundary windows, about 2 % more, are not counted):
+#   per field: two WENO5 reconstructions of 69 (candidate values 16, smoothness
+#   indicators 33, weights and their normalisation 20), the split values at the point
+#   (6), the interface flux sum and difference (3), the stage state and update (5):
+#   152;
+#   per point, Euler: u, p, the flux vector and the wave speed (15);
+#   reactive Euler: the same from the primitives (15) in the bulk precision, and the
+#   temperature inversion with the Arrhenius rate (13) in FP64.
+# (FP32 part, FP64 part) of the FP32 forms; the FP64 form does all of it in FP64.
+WENO_FLOP = {"euler": (3 * 152 + 15, 0), "reactive_euler": (4 * 152 + 15, 13)}
+VALU_PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}
+# steps of the accuracy runs of the other configurations: their stated length, but 20
+# for the single 2^20-point detonation (the serial oracle takes about 4 s per step)
+ACC_STEPS = {"c5": 20}
+
+
+def _ref_job(args):
+    pr, steps = args
+    import oracle
+    return oracle.run(pr.replace(precision="fp64"), steps)
+
+
+def run_other(name, steps, warmup, accuracy=True, workers=16):
+    """Timing of both forms of another configuration, in the batched launch form with
+    HIP graphs, and (accuracy) the error of each form against the oracle per field after
+    the configuration's stated length, in the same launch form."""
+    import multiprocessing as mp
+    from paper_2204_01133_amd import binding
     desc, make = OTHER_CONFIGS[name]
     base = make()
     pts = W.total_points(base)
     stages = {"rk4": 4, "ssprk3": 3, "rk2": 2, "fe": 1}[base[0].rk]
+    acc_steps = ACC_STEPS.get(name, base[0].steps)
+    ns = np.array([p.n for p in base])
+    check = sorted({int(ns.argmin()), int(ns.argmax())})        # problems compared with the oracle
+    pool = refs = None
+    if accuracy:
+        pool = mp.get_context("fork").Pool(min(workers, len(check)))
+        refs = pool.map_async(_ref_job, [(base[b], acc_steps) for b in check])
     forms = {}
     warmup = warmup_steps(warmup, steps)
+    g = graph_len(steps)
     for prec in ("fp32c", "fp64"):
         prs = [p.replace(precision=prec) for p in base]
-        s, t, _ = time_form(prs, steps, warmup)
-        from paper_2204_01133_amd import binding
+        s, t, _, g = time_form(prs, steps, warmup)
         nbytes = algorithmic_bytes_per_step(prs, s)["total"]
         gbs = nbytes * steps / t / 1e9
-        forms[prec + "_batched"] = {"value": pts * stages * steps / t, "ms_per_step": t * 1000.0 / steps,
-                                    "launches_per_step": s.query(binding.Q_NUM_GROUPS),
-                                    "tiles": s.query(binding.Q_NUM_TILES),
-                                    "algorithmic_bytes_per_step": nbytes, "hbm_gbs": gbs,
-                                    "hbm_frac": gbs / HBM_PEAK_GBS}
+        f = {"value": pts * stages * steps / t, "ms_per_step": t * 1000.0 / steps,
+             "launches_per_step": s.query(binding.Q_NUM_GROUPS), "tiles": s.query(binding.Q_NUM_TILES),
+             "algorithmic_bytes_per_step": nbytes, "hbm_gbs": gbs, "hbm_frac": gbs / HBM_PEAK_GBS}
+        s.close()
+        if base[0].pde in WENO_FLOP:
+            f32, f64 = WENO_FLOP[base[0].pde]
+            if prec == "fp64":
+                f32, f64 = 0, f32 + f64
+            ups = pts * stages / (t / steps)               # point-stage updates per second
+            t32, t64 = ups * f32 / 1e12, ups * f64 / 1e12
+            f["valu"] = {"bound": "alu", "flop_per_point_stage": {"f32": f32, "f64": f64},
+                         "achieved_tflops": {"f32": t32, "f64": t64},
+                         "peak_tflops": VALU_PEAK_TFLOPS,
+                         "frac": t32 / VALU_PEAK_TFLOPS["f32"] + t64 / VALU_PEAK_TFLOPS["f64"]}
+        forms[prec + "_batched"] = f
+    if accuracy:
+        ref = dict(zip(check, refs.get()))
+        pool.close()
+        for prec in ("fp32c", "fp64"):
+            prs = [p.replace(precision=prec) for p in base]
+            from paper_2204_01133_amd import ATSolver
+            s = ATSolver(prs, graph_steps=graph_len(acc_steps))
+            s.batch_step(acc_steps)
+            errs = {int(b): field_errs(prs[b], s.state(b), ref[b]) for b in check}
+            s.close()
+            forms[prec + "_batched"]["accuracy"] = {
+                "steps": acc_steps, "problems": {str(b): {"n": int(ns[b]), "max_norm_err_per_field": e}
+                                                 for b, e in errs.items()},
+                "max_norm_err_vs_oracle": max(max(e) for e in errs.values())}
     line = {"metric": "grid-point RK-stage updates/s", "unit": "grid-point RK-stage updates/s",
             "config": {"workload": desc, "problems": len(base), "total_points": pts, "stages": stages,
-                       "form": "at_batch_step, HIP graph of 50 steps"},
+                       "form": f"at_batch_step, HIP graph of {g} steps"},
             "steps": steps, "warmup": warmup, "data": "synthetic", "forms": forms}
     print(json.dumps(line))
 
@@ -176,7 +292,10 @@ def main():
                     help="time only the headline FP32 batched form (profiler runs)")
     ap.add_argument("--sample", type=int, default=128, help="problems in the oracle sample")
     ap.add_argument("--config", default="c3", choices=["c3"] + sorted(OTHER_CONFIGS),
-                    help="c3 (default): the headline line; others: timing of both forms only")
+                    help="c3 (default): the headline line; others: both forms, timing and accuracy")
+    ap.add_argument("--no-accuracy", action="store_true", help="other configurations: timing only")
+    ap.add_argument("--cpu-steps", type=int, default=800,
+                    help="steps of the oracle sample timed for cpu_baseline (at least the GPU's)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the AT batch shards by "
@@ -188,8 +307,13 @@ def main():
         print("no GPU visible: libat has no CPU path", file=sys.stderr)
         sys.exit(1)
 
+    # worker processes of the oracle: the host's CPUs this process may use, at most 16
+    # (the CPU share of one GPU on a shared GPU host)
+    info = host_info()
+    workers = max(1, min(16, info["affinity"] or 1))
+
     if args.config != "c3":
-        run_other(args.config, args.steps, args.warmup)
+        run_other(args.config, args.steps, args.warmup, accuracy=not args.no_accuracy, workers=workers)
         return
 
     base = W.batched_adr_c3()
@@ -199,7 +323,7 @@ def main():
 
     # headline: FP32 compensated, batched + graph
     prs32 = [p.replace(precision="fp32c") for p in base]
-    s32, t32, wall32 = time_form(prs32, K, Wm)
+    s32, t32, wall32, g32 = time_form(prs32, K, Wm)
     bytes32 = algorithmic_bytes_per_step(prs32, s32)
     from paper_2204_01133_amd import binding
     launches = s32.query(binding.Q_NUM_GROUPS)      # tile-kernel launches per batched step
@@ -215,33 +339,31 @@ def main():
 
     # FP64 batched, FP64 plain (one launch per problem, fewer steps: launch bound)
     prs64 = [p.replace(precision="fp64") for p in base]
-    s64, t64, _ = time_form(prs64, K, Wm)
+    s64, t64, _, _ = time_form(prs64, K, Wm)
     bytes64 = algorithmic_bytes_per_step(prs64, s64)
     # FP32 batched with a 4-byte state (the low part is not kept across steps)
     prsf = [p.replace(precision="fp32") for p in base]
-    sf, tf, _ = time_form(prsf, K, Wm)
+    sf, tf, _, _ = time_form(prsf, K, Wm)
     bytesf = algorithmic_bytes_per_step(prsf, sf)
     kp = max(2, min(20, K // 50))
-    _, tplain, _ = time_form(prs64, kp, 2, method="step", graph_steps=0)
+    _, tplain, _, _ = time_form(prs64, kp, 2, method="step", graph_steps=0)
 
     # accuracy of both forms against the oracle (equal stated error), sampled problems
     idx = list(range(0, len(base), max(1, len(base) // args.sample)))[: args.sample]
     total_steps = K + Wm
-    workers = 1
-    try:
-        workers = max(1, min(16, len(os.sched_getaffinity(0))))
-    except Exception:
-        workers = max(1, min(16, os.cpu_count() or 1))
+    # the oracle runs the sample for at least cpu_steps steps (about 15 s of CPU), so that
+    # its rate is not set by a short GPU run; the errors are taken at the GPU's step count
+    cpu_steps = max(total_steps, args.cpu_steps)
     sample_pts = sum(base[i].n for i in idx)
     if args.no_cpu_baseline:
         err32 = err64 = errf = None
         cpu_rate, owall, ocpu = None, 0.0, 0.0
     else:
-        refs, owall, ocpu = oracle_sample(base, idx, total_steps, workers)
+        refs, owall, ocpu = oracle_sample(base, idx, total_steps, cpu_steps, workers)
         err32 = max(norm_err(s32.state(i), r) for i, r in zip(idx, refs))
         err64 = max(norm_err(s64.state(i), r) for i, r in zip(idx, refs))
         errf = max(norm_err(sf.state(i), r) for i, r in zip(idx, refs))
-        cpu_rate = sample_pts * S * total_steps / owall
+        cpu_rate = sample_pts * S * cpu_steps / owall
 
     traffic = None
     try:
@@ -273,7 +395,7 @@ def main():
             "problems": len(base),
             "total_points": total_pts,
             "stages": S,
-            "form": "at_batch_step, FP32 compensated state, HIP graph of 50 steps",
+            "form": f"at_batch_step, FP32 compensated state, HIP graph of {g32} steps",
             "parallelism": "1 GPU",
         },
         "roofline": {
@@ -292,11 +414,13 @@ def main():
             "value": cpu_rate,
             "unit": "grid-point RK-stage updates/s",
             "cores": workers,
-            "per_core": sample_pts * S * total_steps / ocpu if ocpu > 0 else None,
+            "per_core": sample_pts * S * cpu_steps / ocpu if ocpu > 0 else None,
             "kind": "oracle",
             "sample": f"{len(idx)} of {len(base)} problems (every {len(base) // len(idx)}th, "
-                      f"{sample_pts} points), {total_steps} steps, FP64 serial C oracle, "
-                      f"{workers} processes, {ocpu:.1f} s CPU; per_core = updates per CPU-second of one process",
+                      f"{sample_pts} points), {cpu_steps} steps, FP64 serial C oracle, "
+                      f"{workers} worker processes started before the clock, {ocpu:.1f} s CPU in "
+                      f"{owall:.2f} s; per_core = updates per CPU-second of one process",
+            "host": info,
         },
         "forms": {
             "fp32c_batched": {"value": value, "ms_per_step": ms_step, "max_norm_err_vs_oracle": err32,
