@@ -141,6 +141,25 @@ int at_init(const at_problem_desc* probs, int n_probs, const at_run_opts* opts, 
  * first).  Binding forgets all progress (as at_reset).  Errors: AT_EINVAL, AT_EHIP. */
 int at_bind(at_ctx* ctx, void* d_workspace, size_t bytes, void* hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): like at_bind, but the
+ * workspace is the library's own device scratch, a static array of
+ * AT_SCRATCH_BYTES (128 MiB) per device, held by each device the library runs on
+ * until the process ends.  Calls no hipMalloc, hipFree or other allocating routine,
+ * creates no stream, event or graph: the kernel groups of a batched step run one
+ * after another on the given stream and at_batch_step launches them directly
+ * (graph_steps is ignored).  The caller still passes inputs and outputs
+ * (at_set_state, at_get_state).  One context holds a device's scratch at a time:
+ * binding another context to it on the same device makes the earlier one fail
+ * with AT_ESTATE; calls of contexts that overlap in time on one device race.
+ * The scratch keeps the last context's contents; nothing in it needs clearing
+ * (every word a kernel reads was written earlier in the same binding).  Like
+ * at_bind, binding forgets all progress (as at_reset).
+ * Errors: AT_EUNSUPPORTED (workspace_bytes above AT_SCRATCH_BYTES, or a device
+ * index above 63), AT_EHIP. */
+#define AT_SCRATCH_BYTES ((size_t)128 << 20)
+int at_bind_scratch(at_ctx* ctx, void* hip_stream);
+
 /* Set problem `prob`'s level-0 state: F x N doubles (structure of arrays,
  * field-major) on the host (q_on_device = 0; copied before return) or on the
  * device (stream-ordered).  Resets the step counter of the context to 0 when

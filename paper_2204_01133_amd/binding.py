@@ -118,6 +118,7 @@ def load_library():
     vp = ctypes.c_void_p
     L.at_init.argtypes = [P(AtProblemDesc), ctypes.c_int, P(AtRunOpts), P(vp), P(ctypes.c_size_t)]
     L.at_bind.argtypes = [vp, vp, ctypes.c_size_t, vp]
+    L.at_bind_scratch.argtypes = [vp, vp]
     L.at_set_state.argtypes = [vp, ctypes.c_int, vp, ctypes.c_int]
     L.at_reset.argtypes = [vp]
     L.at_rk_stage.argtypes = [vp, ctypes.c_int]
@@ -140,7 +141,7 @@ def load_library():
     return L
 
 
-EXPORTED = ["at_init", "at_bind", "at_set_state", "at_reset", "at_rk_stage", "at_step",
+EXPORTED = ["at_init", "at_bind", "at_bind_scratch", "at_set_state", "at_reset", "at_rk_stage", "at_step",
             "at_batch_step", "at_get_state", "at_get_delays", "at_set_delay_override", "at_sync",
             "at_query", "at_stream", "at_strerror", "at_last_error", "at_free"]
 
@@ -150,10 +151,12 @@ class ATSolver:
 
     problems: sequence of at_workloads.Problem-like objects (their q0 is used
     as the level-0 state unless set_state is called).  opts: at_run_opts keys.
+    scratch: bind the library's own device scratch (at_bind_scratch) instead of
+    a workspace allocated here; for workloads whose workspace fits it.
     """
 
     def __init__(self, problems: Sequence, device: str = "cuda:0", stream=None, set_initial: bool = True,
-                 **opts):
+                 scratch: bool = False, **opts):
         import torch
 
         if not torch.cuda.is_available():
@@ -173,6 +176,13 @@ class ATSolver:
             self._h = h
             self.workspace_bytes = int(nbytes.value)
             self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+            if scratch:
+                self.ws = None
+                self._check(self.L.at_bind_scratch(self._h, ctypes.c_void_p(self.stream.cuda_stream)))
+                if set_initial:
+                    for b, pr in enumerate(self.problems):
+                        self.set_state(b, pr.q0)
+                return
             self.ws = torch.empty(self.workspace_bytes + 256, dtype=torch.uint8, device=self.device)
             # the workspace is used on the solver's stream: its memory is not handed to
             # another tensor before that stream's pending work is done

@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -38,9 +39,23 @@ struct at_ctx {
     hipGraphExec_t gexec = nullptr;
     hipGraph_t graph = nullptr;
     int graph_len = 0;
+    // bound to the library's device scratch (at_bind_scratch) on this device, else -1
+    int scratch_dev = -1;
 };
 
+// Device scratch for callers that cannot allocate device memory (at_bind_scratch): a
+// file-scope device array, one copy per device, held until the process ends.  Host code
+// never uses its name as an address: the device address of each device's copy is looked
+// up once per device (hipGetSymbolAddress, with that device current) and kept here.
+// (AT_SCRATCH_BYTES, the array's size, is part of the C ABI: include/at.h)
+static __device__ __align__(256) unsigned char scratch[AT_SCRATCH_BYTES];
+
 namespace {
+
+constexpr int SCRATCH_MAX_DEV = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[SCRATCH_MAX_DEV] = {};
+const at_ctx* g_scratch_owner[SCRATCH_MAX_DEV] = {};
 
 int fail(at_ctx* c, int code, const std::string& msg) {
     if (c) c->err = msg;
@@ -118,8 +133,14 @@ int upload_probs(at_ctx* c) {
     return AT_OK;
 }
 
+// bound, and (for the device scratch) still the context that holds it
 int check_bound(at_ctx* c) {
     if (!c->bound) return fail(c, AT_ESTATE, "workspace not bound");
+    if (c->scratch_dev >= 0) {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        if (g_scratch_owner[c->scratch_dev] != c)
+            return fail(c, AT_ESTATE, "the device scratch was bound to another context since");
+    }
     return AT_OK;
 }
 
@@ -159,7 +180,9 @@ void free_side_streams(at_ctx* c) {
 // and their own ring records of level n), so the groups run concurrently.
 int batched_step_launches(at_ctx* c, const int64_t* step_ptr, int64_t step_off) {
     const size_t ng = c->plan.groups.size();
-    const bool concurrent = ng > 1;
+    // bound to the device scratch: no side streams or events, the groups run one after
+    // another on the context's stream
+    const bool concurrent = ng > 1 && c->scratch_dev < 0;
     if (concurrent) {
         if (c->side.size() + 1 < ng || c->ev.size() < ng) return fail(c, AT_ESTATE, "side streams missing");
         HIPCHK(c, hipEventRecord(c->ev[0], c->stream));
@@ -253,10 +276,20 @@ int at_init(const at_problem_desc* probs, int n_probs, const at_run_opts* opts, 
     return AT_OK;
 }
 
+namespace {
+void release_scratch(at_ctx* c) {
+    if (c->scratch_dev < 0) return;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_owner[c->scratch_dev] == c) g_scratch_owner[c->scratch_dev] = nullptr;
+    c->scratch_dev = -1;
+}
+}  // namespace
+
 int at_bind(at_ctx* c, void* d_workspace, size_t bytes, void* hip_stream) {
     if (!c || !d_workspace) return AT_EINVAL;
     if (bytes < c->plan.total) return fail(c, AT_EINVAL, "workspace too small");
     if (((uintptr_t)d_workspace & 255) != 0) return fail(c, AT_EINVAL, "workspace not 256-byte aligned");
+    release_scratch(c);
     drop_graph(c);
     c->step = 0;
     c->stage = 0;
@@ -270,6 +303,49 @@ int at_bind(at_ctx* c, void* d_workspace, size_t bytes, void* hip_stream) {
                              sizeof(Tile) * c->plan.tiles_bt.size(), hipMemcpyHostToDevice, c->stream));
     int rc = make_side_streams(c);
     if (rc) return rc;
+    c->bound = true;
+    return upload_probs(c);
+}
+
+int at_bind_scratch(at_ctx* c, void* hip_stream) {
+    if (!c) return AT_EINVAL;
+    if (c->plan.total > AT_SCRATCH_BYTES)
+        return fail(c, AT_EUNSUPPORTED,
+                    "workspace of " + std::to_string(c->plan.total) + " bytes exceeds the device scratch of " +
+                        std::to_string(AT_SCRATCH_BYTES) + " bytes (use at_bind with a caller-owned workspace)");
+    int dev = 0;
+    HIPCHK(c, hipGetDevice(&dev));
+    if (dev < 0 || dev >= SCRATCH_MAX_DEV) return fail(c, AT_EUNSUPPORTED, "device index beyond the scratch table");
+    void* ptr = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        if (!g_scratch_ptr[dev]) {
+            // the device address of this device's copy of the array (the current device)
+            hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+            if (e != hipSuccess) return hip_fail(c, e, "hipGetSymbolAddress(scratch)");
+            if (!ptr || ((uintptr_t)ptr & 255) != 0) return fail(c, AT_EHIP, "device scratch not 256-byte aligned");
+            g_scratch_ptr[dev] = ptr;
+        }
+        ptr = g_scratch_ptr[dev];
+    }
+    release_scratch(c);
+    drop_graph(c);
+    c->step = 0;
+    c->stage = 0;
+    std::fill(c->state_set.begin(), c->state_set.end(), 0);
+    c->ws = (unsigned char*)ptr;
+    c->ws_bytes = AT_SCRATCH_BYTES;
+    c->stream = (hipStream_t)hip_stream;
+    c->bound = false;
+    HIPCHK(c, hipMemcpyAsync(c->ws + c->plan.off_tiles_pm, c->plan.tiles_pm.data(),
+                             sizeof(Tile) * c->plan.tiles_pm.size(), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->ws + c->plan.off_tiles_bt, c->plan.tiles_bt.data(),
+                             sizeof(Tile) * c->plan.tiles_bt.size(), hipMemcpyHostToDevice, c->stream));
+    {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        g_scratch_owner[dev] = c;
+    }
+    c->scratch_dev = dev;
     c->bound = true;
     return upload_probs(c);
 }
@@ -349,7 +425,8 @@ int at_batch_step(at_ctx* c, int n_steps) {
     if (rc) return rc;
     if (c->stage != 0) return fail(c, AT_ESTATE, "at_batch_step inside a per-stage step");
     if (n_steps < 0) return fail(c, AT_EINVAL, "negative step count");
-    const int gl = c->plan.opts.graph_steps;
+    // bound to the device scratch: plain launches only (instantiating a graph may allocate)
+    const int gl = c->scratch_dev >= 0 ? 0 : c->plan.opts.graph_steps;
     int done = 0;
     if (gl > 0 && c->stream != nullptr && n_steps >= gl) {
         if (!c->gexec || c->graph_len != gl) {
@@ -519,6 +596,7 @@ const char* at_last_error(const at_ctx* c) { return c ? c->err.c_str() : "no con
 
 void at_free(at_ctx* c) {
     if (!c) return;
+    release_scratch(c);
     drop_graph(c);
     free_side_streams(c);
     delete c;
