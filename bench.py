@@ -74,6 +74,7 @@ def algorithmic_bytes_per_step(prs, solver) -> dict:
 
 
 GRAPH_STEPS = 50
+WARMUP_S = 0.25     # seconds of untimed stepping before each timed form
 
 
 def graph_len(steps, graph_steps=GRAPH_STEPS):
@@ -101,6 +102,12 @@ def time_form(prs, steps, warmup, method="batch_step", graph_steps=GRAPH_STEPS, 
         run = getattr(s, method)
         run(warmup_steps(warmup, steps, g) if method == "batch_step" else warmup)
         torch.cuda.synchronize()
+        # keep stepping (untimed) until the GPU has been busy for WARMUP_S, so that a short
+        # timed run is not taken at the idle clock
+        t_w = time.perf_counter()
+        while method == "batch_step" and time.perf_counter() - t_w < WARMUP_S:
+            run(max(g, 1))
+            torch.cuda.synchronize()
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         t0 = time.perf_counter()
@@ -439,6 +446,7 @@ def main():
             "stated_error_bound": 2e-6,
         },
         "wall_s_timed": wall32,
+        "warmup_s_extra": WARMUP_S,
     }
     print(json.dumps(line))
 

@@ -301,6 +301,8 @@ int at_bind(at_ctx* c, void* d_workspace, size_t bytes, void* hip_stream) {
                              sizeof(Tile) * c->plan.tiles_pm.size(), hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(c->ws + c->plan.off_tiles_bt, c->plan.tiles_bt.data(),
                              sizeof(Tile) * c->plan.tiles_bt.size(), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->ws + c->plan.off_peoff, c->plan.peoff.data(),
+                             sizeof(int32_t) * c->plan.peoff.size(), hipMemcpyHostToDevice, c->stream));
     int rc = make_side_streams(c);
     if (rc) return rc;
     c->bound = true;
@@ -341,6 +343,8 @@ int at_bind_scratch(at_ctx* c, void* hip_stream) {
                              sizeof(Tile) * c->plan.tiles_pm.size(), hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(c->ws + c->plan.off_tiles_bt, c->plan.tiles_bt.data(),
                              sizeof(Tile) * c->plan.tiles_bt.size(), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->ws + c->plan.off_peoff, c->plan.peoff.data(),
+                             sizeof(int32_t) * c->plan.peoff.size(), hipMemcpyHostToDevice, c->stream));
     {
         std::lock_guard<std::mutex> lk(g_scratch_mu);
         g_scratch_owner[dev] = c;

@@ -129,6 +129,7 @@ int emu_init(const at_problem_desc* probs, int n, const at_run_opts* opts, void*
     c->base = (unsigned char*)(((uintptr_t)c->ws.data() + 255) & ~uintptr_t(255));
     // poison the state and ring so that reads of never-written data give NaN
     std::memset(c->base, 0xff, c->plan.total);
+    std::memcpy(c->base + c->plan.off_peoff, c->plan.peoff.data(), sizeof(int32_t) * c->plan.peoff.size());
     c->ov_step0.assign(n, 0);
     c->ov_n.assign(n, 0);
     sync_probs(*c);

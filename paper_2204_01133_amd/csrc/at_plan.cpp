@@ -177,6 +177,10 @@ int make_plan(const at_problem_desc* probs, int n_probs, const at_run_opts* opts
         pi.J = levels_of(d.scheme, d.mode, d.at_levels);
         pi.D = d.mode == AT_SYNC ? 1 : d.kmax + pi.J;
         pi.st_elems = (int64_t)pi.F * d.n;
+        if (d.n >= ((int64_t)1 << 31)) {
+            err = fmt("problem %lld: N = %lld is above the 32-bit point index range", b, (long long)d.n);
+            return AT_EUNSUPPORTED;
+        }
         // the kernels address each array with 32-bit offsets: every array under 4 GiB
         if (pi.st_elems * (int64_t)MAXS * 8 >= ((int64_t)1 << 32)) {
             err = fmt("problem %lld: F x N = %lld state elements exceed the 32-bit offset range", b,
@@ -333,6 +337,13 @@ int make_plan(const at_problem_desc* probs, int n_probs, const at_run_opts* opts
     plan.off_tpd_pm = o; o = align256(o + sizeof(ProbDev) * plan.tiles_pm.size());
     plan.off_tpd_bt = o; o = align256(o + sizeof(ProbDev) * plan.tiles_bt.size());
     plan.off_step = o; o = align256(o + 64);
+    plan.peoff.clear();
+    plan.peoff.reserve((size_t)(plan.total_pes + n_probs));
+    for (int b = 0; b < n_probs; ++b) {
+        const at_problem_desc& d = plan.desc[b];
+        for (int64_t k = 0; k <= d.p; ++k) plan.peoff.push_back((int32_t)((k * d.n) / d.p));
+    }
+    plan.off_peoff = o; o = align256(o + sizeof(int32_t) * plan.peoff.size());
     plan.state_bytes_per_step = 0;
     plan.strip_bytes_per_step = 0;
     for (int b = 0; b < n_probs; ++b) {
@@ -415,6 +426,21 @@ void fill_probdev(const Plan& plan, int b, unsigned char* base, ProbDev& P, int6
             P.lin_m[o - 1] = d.c * a1 + d.alpha * a2;
         }
     }
+    // FP32 copies (round to nearest, as the device's conversions)
+    double c0 = 0.0;
+    for (int o = 0; o < 4; ++o) {
+        P.lpf[o] = (float)P.lin_p[o];
+        P.lmf[o] = (float)P.lin_m[o];
+        c0 += (double)P.lpf[o] + (double)P.lmf[o];
+    }
+    P.c0f = (float)c0;
+    P.rlf = d.pde == AT_PDE_ADR_LOGISTIC ? (float)d.r : 0.f;
+    P.dtf = (float)d.dt;
+    P.cf = (float)d.c;
+    P.rf = (float)d.r;
+    P.alphaf = (float)d.alpha;
+    P.inv_dxf = (float)P.inv_dx;
+    P.inv_dx2f = (float)P.inv_dx2;
     int S;
     rk_tableau(d.rk, &S, P.a, P.bw);
     for (int w = 0; w < 2; ++w) {
@@ -422,6 +448,8 @@ void fill_probdev(const Plan& plan, int b, unsigned char* base, ProbDev& P, int6
         P.st_lo[w] = d.precision == AT_FP32C ? (void*)(base + pi.off_lo[w]) : nullptr;
     }
     P.ring = base + pi.off_ring;
+    P.peoff = (int32_t*)(base + plan.off_peoff) + (pi.pe_base + b);
+    P.inv_p = 1.0 / (double)d.p;
     P.rec_bytes = pi.rec_bytes;
     P.kbuf = pi.kbuf_len ? (void*)(base + pi.off_kbuf) : nullptr;
     P.kbuf_len = pi.kbuf_len;

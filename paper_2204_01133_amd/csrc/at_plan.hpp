@@ -60,6 +60,10 @@ struct Plan {
     // off_tpd_*: one copy of its problem's descriptor per tile (same order as the tile
     // lists), so that a workgroup reads its tile and descriptor in one round trip
     size_t off_probs, off_tiles_pm, off_tiles_bt, off_tpd_pm, off_tpd_bt, off_step, total;
+    // first point of every PE, floor(p N / P) for p = 0..P, of every problem in turn (problem
+    // b's P + 1 entries start at entry pe_base + b); uploaded to off_peoff by the binding
+    size_t off_peoff;
+    std::vector<int32_t> peoff;
     int64_t total_points, total_pes;
     int64_t state_bytes_per_step, strip_bytes_per_step;
     int max_jmax;

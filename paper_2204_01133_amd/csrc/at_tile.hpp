@@ -120,6 +120,15 @@ __device__ __forceinline__ void lds_copy_word(float* lds_wave, int lane, const f
 inline void lds_copy_word(float* lds_wave, int lane, const float* g, uint32_t i) { lds_wave[lane] = g[i]; }
 #endif
 
+// A scheduling fence: the compiler moves no instruction across it (keeps the loads of a
+// group of points from being hoisted above the arithmetic of the previous group, which
+// would need more registers than the occupancy target allows).  Nothing on the host.
+#if defined(__HIP_DEVICE_COMPILE__)
+__device__ __forceinline__ void sched_fence() { __builtin_amdgcn_sched_barrier(0); }
+#else
+inline void sched_fence() {}
+#endif
+
 // Wait for the wave's vector-memory loads (vmcnt(0) on the GPU; nothing on the host).
 #if defined(__HIP_DEVICE_COMPILE__)
 __device__ __forceinline__ void vm_drain() { __builtin_amdgcn_s_waitcnt(0x0F70); }
@@ -154,10 +163,17 @@ struct ProbDev {
     double a[MAXS][MAXS];
     double bw[MAXS];
     double lin_p[4], lin_m[4];   // scalar FD kind: weights of u_{i+o} - u_i and u_{i-o} - u_i
+    // FP32 copies of the constants of the FP32 forms, rounded on the host (so that they
+    // arrive in scalar registers): lin_p, lin_m, their sum, the logistic rate (0 unless the
+    // PDE has the logistic term), dt, c, r, alpha, 1/dx, 1/dx^2
+    float lpf[4], lmf[4];
+    float c0f, rlf, dtf, cf, rf, alphaf, inv_dxf, inv_dx2f;
     // memory (device addresses; host addresses in the emulation)
     void* st_hi[2];          // state ping-pong: F x N (FP64 value or FP32 hi)
     void* st_lo[2];          // FP32 forms: lo parts
     void* ring;              // strip ring: D x P x 2 records of rec_bytes
+    const int32_t* peoff;    // first point of PE p, p = 0..P (floor(p N / P))
+    double inv_p;            // 1 / P
     int64_t rec_bytes;
     void* kbuf;              // stage right-hand sides for the per-stage entry point
     uint8_t* ov;             // delay override [ov_n][P][2]
@@ -183,6 +199,9 @@ struct PhysP {
     float cf, alphaf, rf, inv_dxf, inv_dx2f;     // FP32 copies for the FP32 forms
     double lp[4], lm[4];                           // scalar FD kind: combined stencil
     float lpf[4], lmf[4];
+    float c0f;                                     // FP32 scalar kind: sum of lpf and lmf
+    float rlf;                                     // FP32 scalar kind: logistic rate (0 without)
+    float dtf;                                     // FP32 forms: dt
 };
 
 #if defined(__HIP_DEVICE_COMPILE__)
@@ -194,6 +213,9 @@ __device__ __forceinline__ double uni(double v) {
     u.i[1] = __builtin_amdgcn_readfirstlane(u.i[1]);
     return u.d;
 }
+__device__ __forceinline__ float uni(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, v)));
+}
 __device__ __forceinline__ int64_t uni(int64_t v) {
     union { int64_t l; int i[2]; } u;
     u.l = v;
@@ -203,6 +225,7 @@ __device__ __forceinline__ int64_t uni(int64_t v) {
 }
 #else
 inline int uni(int v) { return v; }
+inline float uni(float v) { return v; }
 inline double uni(double v) { return v; }
 inline int64_t uni(int64_t v) { return v; }
 #endif
@@ -234,12 +257,18 @@ AT_HD AT_FI ProbDev uniform_copy(const AT_CONST ProbDev& P) {
     for (int i = 0; i < 4; ++i) {
         u.lin_p[i] = uni(P.lin_p[i]);
         u.lin_m[i] = uni(P.lin_m[i]);
+        u.lpf[i] = uni(P.lpf[i]);
+        u.lmf[i] = uni(P.lmf[i]);
     }
+    u.c0f = uni(P.c0f); u.rlf = uni(P.rlf); u.dtf = uni(P.dtf); u.cf = uni(P.cf); u.rf = uni(P.rf);
+    u.alphaf = uni(P.alphaf); u.inv_dxf = uni(P.inv_dxf); u.inv_dx2f = uni(P.inv_dx2f);
     for (int w = 0; w < 2; ++w) {
         u.st_hi[w] = uni_ptr(P.st_hi[w]);
         u.st_lo[w] = uni_ptr(P.st_lo[w]);
     }
     u.ring = uni_ptr(P.ring);
+    u.peoff = uni_ptr(P.peoff);
+    u.inv_p = uni(P.inv_p);
     u.rec_bytes = uni(P.rec_bytes);
     u.kbuf = uni_ptr(P.kbuf);
     u.ov = uni_ptr(P.ov);
@@ -362,8 +391,12 @@ struct Layout {
         o = 0;
         // main region, two stage parities (a stage reads one, writes the next stage's
         // quantities into the other); the FP32 scalar kind shares its hi part
+        // FP32 scalar kind: the lo parts of both stage parities, interleaved (word 2e + parity),
+        // at offset 0 of the launch's LDS, so that the own points' stencil reads take
+        // their neighbour offsets as instruction immediates; then the hi parts
+        if (C::HILO) { o_glo = o; o += align16(2 * EXM * 4); }
         o_g = o;     o += align16((C::HILO ? 1 : 2) * C::NQ * EXM * sl);
-        o_glo = o;   o += C::HILO ? align16(2 * EXM * 4) : 0;
+        if (!C::HILO) o_glo = o;
         o_lam = o;   o += C::WENO ? align16(2 * EXM * sl) : 0;
         o_flux = o;  o += C::WENO ? align16(C::F * EXM * sl) : 0;
         if (o < raw_end) o = raw_end;
@@ -528,10 +561,12 @@ AT_HD AT_FI R weno5(R eps, R v0, R v1, R v2, R v3, R v4) {
 template <class C>
 struct TS {
     int e[C::PPT];                                // ext index of the own point (-1: none)
+    uint32_t eb[C::PPT];                          // FP32 scalar kind: e - H (below 2^16)
     typename C::lreal uh[C::PPT][C::F];           // u^n (FP64 value / FP32 hi)
     float ul[C::PPT][C::F];                       // FP32 lo
     typename C::lreal K[C::S][C::PPT][C::F];      // stage right-hand sides (each dies after its last use)
     typename C::lreal acc[C::PPT][C::F];          // sum_s b_s K_s so far (s ascending)
+    float khi[C::PPT];                            // FP32 scalar kind: hi part of K (fixed in a step)
 };
 
 // views of one set of differentiated quantities (main region or one window parity)
@@ -572,7 +607,8 @@ struct Lds {
                 main[par].g[q] = View<L>{(L*)(base + Lo.o_g) + (pg * C::NQ + q) * nm, nm};
                 win[par].g[q] = View<L>{(L*)(base + Lo.o_gw) + (par * C::NQ + q) * nw, nw};
             }
-            main[par].glo = View<float>{(float*)(base + Lo.o_glo) + par * nm, C::HILO ? nm : 0};
+            // interleaved by parity: the lo part of position e is element 2e of the view
+            main[par].glo = View<float>{(float*)(base + Lo.o_glo) + par, C::HILO ? 2 * nm - par : 0};
             main[par].lam = View<L>{(L*)(base + Lo.o_lam) + par * nm, C::WENO ? nm : 0};
             win[par].glo = View<float>{(float*)(base + Lo.o_gwlo) + par * nw, C::HILO ? nw : 0};
             win[par].lam = View<L>{(L*)(base + Lo.o_lamw) + par * nw, C::WENO ? nw : 0};
@@ -804,6 +840,30 @@ AT_HD AT_FI float rhs_adr_hilo(const QV<C>& L, const PhysP& P, int64_t e, float 
     return k;
 }
 
+// FP32 scalar FD kind at an own point whose hi and lo parts the caller holds:
+//   K = khi + sum_o (lpf_o l_{e+o} + lmf_o l_{e-o}) - c0 l_e + r u (1 - u),  u = h_e + l_e,
+// where khi = sum_o lpf_o (h_{e+o} - h_e) + lmf_o (h_{e-o} - h_e) is the hi parts' share, fixed
+// within a step (the hi parts do not change), and the lo parts l are those of the stage.
+// The stencil's weights sum to zero, so this is the stencil of h + l; the lo parts are
+// the small stage increments and compensations, so their products need no difference form.
+// lo2: the interleaved lo parts (element 2e + parity); eb = e - H >= 0, so every neighbour is
+// at a non-negative offset from element 2 eb.
+// Returns the neighbours' share sum_o (lpf_o l_{e+o} + lmf_o l_{e-o}); lc receives l_e.
+template <class C>
+AT_HD AT_FI float hilo_lo_sum(const View<float>& lo2, uint32_t eb, int par, const PhysP& P, float& lc) {
+    float v[2 * C::H + 1];
+#pragma unroll
+    for (int j = 0; j <= 2 * C::H; ++j) v[j] = lo2[2 * (int64_t)(eb + (uint32_t)j) + par];
+    lc = v[C::H];
+    float k = 0.f;
+#pragma unroll
+    for (int o = C::H; o >= 1; --o) {
+        k = fmaf(P.lmf[o - 1], v[C::H - o], k);
+        k = fmaf(P.lpf[o - 1], v[C::H + o], k);
+    }
+    return k;
+}
+
 template <class C>
 AT_HD AT_FI void rhs_at(const QV<C>& L, const PhysP& P, int64_t e, const typename C::qreal* q,
                         typename C::lreal* K) {
@@ -812,6 +872,7 @@ AT_HD AT_FI void rhs_at(const QV<C>& L, const PhysP& P, int64_t e, const typenam
         // -c u_x + alpha u_xx as one central stencil on differences to the centre
         // (the weights of each derivative sum to zero)
         if constexpr (C::HILO) {
+            // windows only (the main region's lo parts are interleaved by parity)
             K[0] = rhs_adr_hilo<C>(L, P, e, L.g[0][e], L.glo[e]);
         } else {
             const LR uc = L.g[0][e];
@@ -903,12 +964,15 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const AT_CONST Pr
     PP.q = uni(P.q); PP.ea = uni(P.ea); PP.b = uni(P.b); PP.mu = uni(P.mu);
     PP.kappa = uni(P.kappa); PP.rhoD = uni(P.rhoD); PP.eps = uni(P.eps);
     PP.inv_dx = uni(P.inv_dx); PP.inv_dx2 = uni(P.inv_dx2); PP.dt = uni(P.dt);
-    PP.cf = (float)PP.c; PP.alphaf = (float)PP.alpha; PP.rf = (float)PP.r;
-    PP.inv_dxf = (float)PP.inv_dx; PP.inv_dx2f = (float)PP.inv_dx2;
+    PP.cf = uni(P.cf); PP.alphaf = uni(P.alphaf); PP.rf = uni(P.rf);
+    PP.inv_dxf = uni(P.inv_dxf); PP.inv_dx2f = uni(P.inv_dx2f);
+    PP.dtf = uni(P.dtf);
+    PP.c0f = uni(P.c0f);
+    PP.rlf = uni(P.rlf);
     if constexpr (C::KIND == K_ADR) {
         for (int o = 0; o < H; ++o) {
             PP.lp[o] = uni(P.lin_p[o]); PP.lm[o] = uni(P.lin_m[o]);
-            PP.lpf[o] = (float)PP.lp[o]; PP.lmf[o] = (float)PP.lm[o];
+            PP.lpf[o] = uni(P.lpf[o]); PP.lmf[o] = uni(P.lmf[o]);
         }
     }
     // memory of the problem (uniform)
@@ -938,7 +1002,7 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const AT_CONST Pr
     const bool use_lo = C::F32 && P.keep_lo;
     const int64_t N = uni(P.n);
     const int J = uni(P.J);
-    const LR dt = LR(PP.dt);
+    const LR dt = C::F32 ? LR(PP.dtf) : LR(PP.dt);
     AT_CHECK(t.npts <= a.npts_max && t.npe <= a.npe_max, "tile size", t.npts, a.npts_max);
     AT_CHECK(J <= a.jmax && J <= JM, "jmax", J, a.jmax);
     AT_CHECK(t.npts <= nth * PPT, "points per thread", t.npts, nth * PPT);
@@ -1018,16 +1082,9 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const AT_CONST Pr
     //   raw u^n on [lo - S*H, lo + npts + S*H) (own points and boundary windows),
     //   PE offsets, delays, delayed strips of the ring, stage inputs (per-stage mode)
     constexpr int SH = S * H;
-    const double invP = 1.0 / (double)Pp;
-    // floor(p N / P), the first point of PE p: estimated in double, then corrected exactly
-    auto pe_offset = [&](int64_t pe) -> int64_t {
-        const int64_t num = pe * N;
-        int64_t lo = (int64_t)((double)num * invP);
-        if (lo * Pp > num) --lo;
-        else if ((lo + 1) * Pp <= num) ++lo;
-        AT_CHECK(lo * Pp <= num && (lo + 1) * Pp > num, "PE offset", lo, num);
-        return lo;
-    };
+    // floor(p N / P), the first point of PE p, from the planner's table
+    const GView<const int32_t> peoff{P.peoff, Pp + 1};
+    auto pe_offset = [&](int64_t pe) -> int64_t { return (int64_t)peoff.ld(pe); };
     constexpr int nrec = S * H * F;              // lo (FP32) or value (FP64) words of a level
     constexpr int nhi = C::F32 ? H * F : 1;      // FP32 hi words of a level
     // FP32 forms: the raw range is copied into LDS directly (no registers), and all
@@ -1380,7 +1437,7 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const AT_CONST Pr
                 }
             });
             if constexpr (C::F32) {
-                const float lo = ts.ul[k][f] + float(dt) * acc;
+                const float lo = ts.ul[k][f] + PP.dtf * acc;
                 vlo = lo;
                 return (Q)ts.uh[k][f] + (Q)lo;
             } else {
@@ -1389,18 +1446,29 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const AT_CONST Pr
             }
         }
     };
+    // own slot k of thread tid: whether it holds a point, and the point's ext position
+    // (the FP32 scalar kind keeps e - H, known non-negative, so that its LDS neighbours sit
+    // at non-negative offsets)
+    auto pt_ok = [&](const TS<C>& ts, int tid, int k) -> bool {
+        if constexpr (C::HILO) return tid + k * nth < t.npts;
+        else return ts.e[k] >= 0;
+    };
+    auto pt_e = [&](const TS<C>& ts, int k) -> int {
+        if constexpr (C::HILO) return (int)ts.eb[k] + H;
+        else return ts.e[k];
+    };
     // quantities of V(s) at own slot k, into the main region of stage parity s & 1
     auto own_quant = [&](const TS<C>& ts, int k, auto sc) {
         constexpr int s = decltype(sc)::value;
         const QV<C>& M = L.main[s & 1];
-        const int e = ts.e[k];
+        const int e = pt_e(ts, k);
         Q q[F];
         float vlo[F];
 #pragma unroll
         for (int f = 0; f < F; ++f) q[f] = own_state(ts, k, f, sc, vlo[f]);
         if constexpr (C::HILO) {
             if (s == s0) M.g[0][e] = ts.uh[k][0];   // hi: fixed within the step, both parities
-            M.glo[e] = vlo[0];
+            M.glo[2 * (int64_t)e] = vlo[0];
         } else {
             put_quant<C>(M, PP, e, q);
         }
@@ -1421,7 +1489,7 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const AT_CONST Pr
         if constexpr (C::HILO) {
             // extrapolated in the load phase
             if (s == s0) M.g[0][e] = L.SOhi[side_idx * H * F + h * F];
-            M.glo[e] = L.SO[sob + (s * H + h) * F];
+            M.glo[2 * (int64_t)e] = L.SO[sob + (s * H + h) * F];
         } else if constexpr (C::KIND == K_ADR) {
             M.g[0][e] = L.SO[sob + (s * H + h) * F];   // extrapolated in the load phase
         } else {
@@ -1470,10 +1538,18 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const AT_CONST Pr
 #pragma unroll
         for (int k = 0; k < PPT; ++k) {
             const int i = tid + k * nth;
-            ts.e[k] = -1;
+            if constexpr (!C::HILO) ts.e[k] = -1;
+            // every per-point register gets a value on every path, so that none of them is
+            // live across the tile loop (a slot without a point is never read)
+            if constexpr (C::HILO) {
+                ts.eb[k] = 0;
+                ts.khi[k] = 0.f;
+                ts.acc[k][0] = 0.f;
+            }
             if (i >= t.npts) continue;
             const int lo = pe_local(i);
-            ts.e[k] = i + 2 * H * lo + H;
+            if constexpr (C::HILO) ts.eb[k] = (uint32_t)(i + 2 * H * lo) & 0xFFFFu;
+            else ts.e[k] = i + 2 * H * lo + H;
             if constexpr (!OWN_REG) {
 #pragma unroll
                 for (int f = 0; f < F; ++f) {
@@ -1528,7 +1604,7 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const AT_CONST Pr
         rt.each([&](int tid, TS<C>& ts) {
 #pragma unroll
             for (int k = 0; k < PPT; ++k)
-                if (ts.e[k] >= 0) own_quant(ts, k, sc);
+                if (pt_ok(ts, tid, k)) own_quant(ts, k, sc);
             for (int idx = first_item(tid, nth, 2); idx < 2 * t.npe * H; idx += nth) {
                 const int side_idx = idx / H, h = idx - side_idx * H;
                 if (first && L.keff[side_idx] == 0) {
@@ -1540,7 +1616,7 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const AT_CONST Pr
                     const QV<C>& W0 = C::HILO ? L.win0 : L.win[0];
 #pragma unroll
                     for (int j = 0; j < NQ; ++j) M.g[j][e] = W0.g[j][wp];
-                    if constexpr (C::HILO) M.glo[e] = W0.glo[wp];
+                    if constexpr (C::HILO) M.glo[2 * (int64_t)e] = W0.glo[wp];
                     if constexpr (C::WENO) M.lam[e] = W0.lam[wp];
                 } else {
                     halo_from_so(side_idx, h, sc);
@@ -1598,17 +1674,36 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const AT_CONST Pr
             if (own_active) {
 #pragma unroll
                 for (int k = 0; k < PPT; ++k) {
-                    const int e = ts.e[k];
-                    if (e < 0) continue;
+                    if (C::HILO && k % 2 == 0 && k > 0) sched_fence();
+                    if (!pt_ok(ts, tid, k)) continue;
+                    const int e = pt_e(ts, k);
                     Q q[F];
-                    float vlo;
+                    float vlo = 0.f;
+                    if constexpr (!C::HILO) {
 #pragma unroll
-                    for (int f = 0; f < F; ++f) q[f] = own_state(ts, k, f, sc, vlo);
+                        for (int f = 0; f < F; ++f) q[f] = own_state(ts, k, f, sc, vlo);
+                    }
                     LR K[F];
-                    // the centre's hi part from registers, its lo part from LDS (holding the
-                    // recomputed lo live as well costs registers)
-                    if constexpr (C::HILO) K[0] = rhs_adr_hilo<C>(Mc, PP, e, ts.uh[k][0], Mc.glo[e]);
-                    else rhs_at<C>(Mc, PP, e, q, K);
+                    if constexpr (C::HILO) {
+                        // the hi parts' share once per step (stage s0 of the launch)
+                        const float hc = ts.uh[k][0];
+                        if (s == s0) {
+                            float kh = 0.f;
+#pragma unroll
+                            for (int o = H; o >= 1; --o) {
+                                kh = fmaf(PP.lmf[o - 1], Mc.g[0][e - o] - hc, kh);
+                                kh = fmaf(PP.lpf[o - 1], Mc.g[0][e + o] - hc, kh);
+                            }
+                            ts.khi[k] = kh;
+                        }
+                        float lc;      // the stage's lo part of the point, as own_quant wrote it
+                        const float lsum = hilo_lo_sum<C>(L.main[0].glo, ts.eb[k], s & 1, PP, lc);
+                        const float u = hc + lc;
+                        float kk = fmaf(-PP.c0f, lc, ts.khi[k] + lsum);
+                        K[0] = fmaf(PP.rlf * u, 1.f - u, kk);
+                    } else {
+                        rhs_at<C>(Mc, PP, e, q, K);
+                    }
 #pragma unroll
                     for (int f = 0; f < F; ++f) {
                         ts.K[s][k][f] = K[f];
@@ -1672,30 +1767,34 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const AT_CONST Pr
                         });
                         hv[f] = L.wu[f][wp];
                         if constexpr (C::F32) {
-                            const float lo = L.wulo[f][wp] + float(dt) * acc;
+                            const float lo = L.wulo[f][wp] + PP.dtf * acc;
                             lvn[f] = lo;
                             L.wq[(s + 1) & 1][f][wp] = lo;
                             qn[f] = (Q)hv[f] + (Q)lo;
-                            strip_out(b, w, s + 1, f, lo, 0.f);
                         } else {
                             const LR v = hv[f] + dt * acc;
                             lvn[f] = 0.f;
                             L.wq[(s + 1) & 1][f][wp] = v;
                             qn[f] = (Q)v;
-                            strip_out(b, w, s + 1, f, v, 0.f);
                         }
                     }
                     // FP32 scalar kind: the window's quantities are its state (hi in wu, lo in
                     // the stage parity's wq, written above), nothing more to write
                     if constexpr (!C::HILO) put_quant<C>(Wn, PP, wp, qn);
-                    // a halo point of a PE side with delay 0: its stage s+1 quantities
+                    // a halo point (left of PE b or right of PE b - 1): its ring record of stage
+                    // s + 1 and, for a PE side of delay 0, its stage s + 1 quantities
                     const int h2 = w - (S - 1) * H;
-                    if (next_active && h2 >= 0 && h2 < 2 * H) {
+                    if ((unsigned)h2 < (unsigned)(2 * H)) {
                         const int side = h2 < H ? 0 : 1, kpe = b - side, h = h2 - side * H;
-                        if (kpe >= 0 && kpe < t.npe && L.keff[2 * kpe + side] == 0) {
-                            const int e = halo_e(kpe, side, h);
-                            if constexpr (C::HILO) Mn.glo[e] = lvn[0];
-                            else put_quant<C>(Mn, PP, e, qn);
+                        if ((unsigned)kpe < (unsigned)t.npe) {
+#pragma unroll
+                            for (int f = 0; f < F; ++f)
+                                rec_store(kpe, side, s + 1, h, f, C::F32 ? (LR)lvn[f] : (LR)qn[f], 0.f);
+                            if (next_active && L.keff[2 * kpe + side] == 0) {
+                                const int e = halo_e(kpe, side, h);
+                                if constexpr (C::HILO) Mn.glo[2 * (int64_t)e] = lvn[0];
+                                else put_quant<C>(Mn, PP, e, qn);
+                            }
                         }
                     }
                 }
@@ -1708,7 +1807,7 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const AT_CONST Pr
     rt.each([&](int tid, TS<C>& ts) {
 #pragma unroll
         for (int k = 0; k < PPT; ++k) {
-            if (ts.e[k] < 0) continue;
+            if (!pt_ok(ts, tid, k)) continue;
             const int64_t x = t.lo + tid + k * nth;
             if (s1 < S - 1) continue;              // per-stage entry point: K_s1 already out
             const GView<LR> dst = st_view<C>(P, nxt);
@@ -1719,7 +1818,7 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const AT_CONST Pr
                 if constexpr (C::F32) {
                     // compensated update: (hi, lo) + dt*acc, TwoSum of hi and (lo + dt*acc)
                     const float hi = ts.uh[k][f];
-                    const float tt = ts.ul[k][f] + float(dt) * acc;
+                    const float tt = ts.ul[k][f] + PP.dtf * acc;
                     const float sum = hi + tt;
                     const float bb = sum - hi;
                     const float err = (hi - (sum - bb)) + (tt - bb);
