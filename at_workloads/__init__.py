@@ -38,6 +38,7 @@ MODES = ("sync", "as", "at")
 RKS = ("fe", "rk2", "ssprk3", "rk4")
 GRANULARITIES = ("per_pe", "per_pe_side", "per_boundary")
 PRECISIONS = ("fp64", "fp32c", "fp32")
+BCS = ("periodic", "nscbc")
 
 # Probability sets of Table dels (Sec. 5): [p0 p1 p2].
 DELAY_SETS = {
@@ -83,6 +84,7 @@ class Problem:
     cdf: Tuple[int, ...] = ()         # () -> uniform on {0..kmax}
     granularity: str = "per_pe"
     at_levels: int = 0                # J time levels of the AT extrapolation (0: scheme default)
+    bc: str = "periodic"              # "periodic", or "nscbc": two ends with non-reflecting conditions
     x0: float = 0.0
     lx: float = 1.0
     c: float = 0.0
@@ -105,7 +107,7 @@ class Problem:
     def __post_init__(self):
         assert self.pde in PDES and self.scheme in SCHEMES and self.mode in MODES
         assert self.rk in RKS and self.granularity in GRANULARITIES
-        assert self.precision in PRECISIONS
+        assert self.precision in PRECISIONS and self.bc in BCS
         self.q0 = np.ascontiguousarray(self.q0, dtype=np.float64).reshape(nfields(self.pde), self.n)
         if self.cdf:
             assert len(self.cdf) == self.kmax, "cdf needs kmax thresholds"
@@ -226,6 +228,37 @@ def reactive_ns_c2(seed: int = 1, n: int = 8192, p: int = 64, kmax: int = 4, mod
     return Problem(pde="reactive_ns", scheme=scheme, n=n, p=p, dt=dt, q0=q0, mode=mode, rk="rk4",
                    kmax=kmax, gamma=gamma, q=q, ea=ea, b=b, mu=2e-5, pr=0.72, le=1.0, seed=seed,
                    precision=precision, steps=steps, name="reactive_ns_c2")
+
+
+def acoustic_wave(n: int = 512, p: int = 8, kmax: int = 2, mode: str = "at", seed: int = 1,
+                  amp: float = 1e-3, width: float = 300.0, x_peak: float = 0.35, u0: float = 0.0,
+                  mu: float = 1e-5, t_end: Optional[float] = None, scheme: str = "fd4",
+                  precision: str = "fp64", cdf: Tuple[int, ...] = ()) -> Problem:
+    """Acoustic pulse in a gas at rest between two non-reflecting ends (the non-reacting
+    case of Sec. 5.1, eq. acIC, non-dimensional): on [0, 1) with rho0 = T0 = p0 = 1 (R = 1),
+    gamma 1.4, c0 = sqrt(gamma),
+        u = u0 + A exp(-B (x - x0)^2),  p = p0 + rho0 c0 (u - u0),  rho = rho0 + rho0 (u - u0) / c0,
+    a right-running simple wave of amplitude A = amp * c0.  No reaction (b = 0), uniform Y.
+    dt = cfl(kmax) dx / (c0 + |u|max); t_end defaults to the time the pulse needs to
+    reach x = 1.2 (past the right end)."""
+    gamma = 1.4
+    c0 = math.sqrt(gamma)
+    x = _grid(n, 0.0, 1.0)
+    dx = 1.0 / n
+    A = amp * c0
+    u = u0 + A * np.exp(-width * (x - x_peak) ** 2)
+    pr_ = 1.0 + c0 * (u - u0)
+    rho = 1.0 + (u - u0) / c0
+    T = pr_ / rho
+    q0 = reactive_conserved(rho, u, T, np.ones(n), gamma, 0.0)
+    dt0 = at_stable_cfl(kmax) * dx / (c0 + abs(u0) + A)
+    if t_end is None:
+        t_end = (1.2 - x_peak) / (c0 + u0)
+    steps = int(math.ceil(t_end / dt0 - 1e-9))
+    dt = t_end / steps
+    return Problem(pde="reactive_ns", scheme=scheme, n=n, p=p, dt=dt, q0=q0, mode=mode, rk="rk4", kmax=kmax,
+                   cdf=cdf, gamma=gamma, q=0.0, ea=1.0, b=0.0, mu=mu, pr=0.72, le=1.0, seed=seed,
+                   precision=precision, steps=steps, bc="nscbc", name="acoustic_wave")
 
 
 def batched_adr_c3(seed: int = 1, n_problems: int = 4096, steps: int = 1000,

@@ -29,6 +29,7 @@ SCHEME_IDS = {"fd2": 0, "fd4": 1, "fd8": 2, "weno5": 3}
 MODE_IDS = {"sync": 0, "as": 1, "at": 2}
 RK_IDS = {"fe": 0, "rk2": 1, "ssprk3": 2, "rk4": 3}
 GRAN_IDS = {"per_pe": 0, "per_pe_side": 1, "per_boundary": 2}
+BC_IDS = {"periodic": 0, "nscbc": 1}
 
 ERRORS = {0: "ok", -1: "invalid argument", -2: "out of memory", -3: "stale: delay beyond kmax",
           -4: "out of range"}
@@ -45,7 +46,7 @@ class OrcProblem(ctypes.Structure):
         ("pde", ctypes.c_int32), ("scheme", ctypes.c_int32), ("mode", ctypes.c_int32),
         ("rk", ctypes.c_int32), ("granularity", ctypes.c_int32), ("kmax", ctypes.c_int32),
         ("n", ctypes.c_int64), ("p", ctypes.c_int32), ("n_cdf", ctypes.c_int32),
-        ("at_levels", ctypes.c_int32), ("pad0", ctypes.c_int32),
+        ("at_levels", ctypes.c_int32), ("bc", ctypes.c_int32),
         ("cdf", ctypes.c_uint64 * 16),
         ("x0", ctypes.c_double), ("lx", ctypes.c_double), ("dt", ctypes.c_double),
         ("c", ctypes.c_double), ("alpha", ctypes.c_double), ("r", ctypes.c_double),
@@ -101,6 +102,8 @@ def load(path: str):
     L.orc_draw.argtypes = [P(OrcProblem), ctypes.c_int64, ctypes.c_int64, ctypes.c_int]
     L.orc_extrap_weights.argtypes = [ctypes.c_int, ctypes.c_int, P(ctypes.c_double)]
     L.orc_rhs_sync.argtypes = [P(OrcProblem), P(ctypes.c_double), P(ctypes.c_double)]
+    L.orc_lodi.argtypes = [P(OrcProblem), ctypes.c_int, ctypes.c_int, P(ctypes.c_double), P(ctypes.c_double),
+                           P(ctypes.c_double)]
     return L
 
 
@@ -125,6 +128,7 @@ def to_struct(pr) -> OrcProblem:
     s.p = pr.p
     s.n_cdf = len(pr.cdf)
     s.at_levels = int(pr.at_levels)
+    s.bc = BC_IDS[getattr(pr, "bc", "periodic")]
     for i, v in enumerate(pr.cdf):
         s.cdf[i] = int(v)
     for name in ("x0", "lx", "dt", "c", "alpha", "r", "gamma", "q", "ea", "b", "mu", "pr", "le",
@@ -239,4 +243,15 @@ def rhs_sync(pr, q: np.ndarray) -> np.ndarray:
     q = np.ascontiguousarray(q, dtype=np.float64).reshape(pr.nf, pr.n)
     out = np.empty_like(q)
     _check(lib().orc_rhs_sync(ctypes.byref(s), _dptr(q), _dptr(out)))
+    return out
+
+
+def lodi(pr, side: int, drop: bool, prim, dprim) -> np.ndarray:
+    """Convective time derivatives of (rho, rho u, rho E, rho Y) at an end point in the
+    characteristic form (non-periodic ends)."""
+    s = to_struct(pr)
+    a = np.ascontiguousarray(prim, dtype=np.float64)
+    d = np.ascontiguousarray(dprim, dtype=np.float64)
+    out = np.empty(4)
+    _check(lib().orc_lodi(ctypes.byref(s), int(side), int(bool(drop)), _dptr(a), _dptr(d), _dptr(out)))
     return out

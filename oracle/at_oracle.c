@@ -280,7 +280,109 @@ static double d2(const double* g, int e, int H, const double* c2, double dx) {
     return s / (dx * dx);
 }
 
-static void rhs_region(const orc_problem* pb, int64_t np, double** g, const double* lam,
+/* ------------------------------------------------------------------------- */
+/* Non-periodic ends (bc = 1).                                                */
+/* Convective terms at an end point in characteristic form (LODI relations of */
+/* Thompson 1987 / Poinsot & Lele 1992, for the one-step-chemistry gas):      */
+/*   L1 = (u - c)(p_x - rho c u_x)    speed u - c                             */
+/*   L2 = u (c^2 rho_x - p_x)         speed u                                 */
+/*   L3 = u Y_x                       speed u                                 */
+/*   L5 = (u + c)(p_x + rho c u_x)    speed u + c                             */
+/* A wave entering the domain (speed > 0 at the left end, < 0 at the right)   */
+/* has its amplitude set to zero (non-reflecting).  With                      */
+/*   d1 = (L2 + (L5 + L1)/2) / c^2,  d2 = (L5 + L1)/2,  d3 = (L5 - L1)/(2 rho c)*/
+/* the time derivatives are rho_t = -d1, u_t = -d3, p_t = -d2, Y_t = -L3, and  */
+/* for the conserved state (rho E = p/(gamma-1) + rho u^2/2 + q rho Y):       */
+/*   (rho)_t   = -d1                                                          */
+/*   (rho u)_t = -(u d1 + rho d3)                                             */
+/*   (rho Y)_t = -(Y d1 + rho L3)                                             */
+/*   (rho E)_t = -(u^2 d1 / 2 + d2/(gamma-1) + rho u d3) + q (rho Y)_t        */
+/* side: 0 left end, 1 right end; drop = 0 keeps every wave (the full         */
+/* convective derivative, for the pins).                                     */
+/* ------------------------------------------------------------------------- */
+int orc_lodi(const orc_problem* pb, int side, int drop, const double* prim, const double* dprim,
+             double* out) {
+    const double rho = prim[0], u = prim[1], p = prim[2], Y = prim[3];
+    const double rx = dprim[0], ux = dprim[1], px = dprim[2], Yx = dprim[3];
+    const double gm = pb->gamma;
+    const double c = sqrt(gm * p / rho);
+    double L1 = (u - c) * (px - rho * c * ux);
+    double L2 = u * (c * c * rx - px);
+    double L3 = u * Yx;
+    double L5 = (u + c) * (px + rho * c * ux);
+    if (drop) {
+        /* incoming: positive speed at the left end, negative at the right end */
+        const double sgn = side == 0 ? 1.0 : -1.0;
+        if (sgn * (u - c) > 0.0) L1 = 0.0;
+        if (sgn * u > 0.0) { L2 = 0.0; L3 = 0.0; }
+        if (sgn * (u + c) > 0.0) L5 = 0.0;
+    }
+    const double d1 = (L2 + 0.5 * (L5 + L1)) / (c * c);
+    const double d2 = 0.5 * (L5 + L1);
+    const double d3 = (L5 - L1) / (2.0 * rho * c);
+    out[0] = -d1;
+    out[1] = -(u * d1 + rho * d3);
+    out[3] = -(Y * d1 + rho * L3);
+    out[2] = -(0.5 * u * u * d1 + d2 / (gm - 1.0) + rho * u * d3) + pb->q * out[3];
+    return ORC_OK;
+}
+
+/* primitives (rho, u, p, T, Y) at ext position e from the reactive NS quantities
+ * C1 = rho u, C2 = rho u^2 + p, u, T, Y (g[0], g[1], g[4], g[5], g[6]) */
+static void rns_prims_at(double** g, int e, double* rho, double* u, double* p, double* T, double* Y) {
+    *u = g[4][e];
+    *T = g[5][e];
+    *Y = g[6][e];
+    *p = g[1][e] - g[0][e] * (*u);
+    *rho = *p / *T;
+}
+
+/* reactive NS right-hand side at a point whose stencil would leave the domain
+ * (bc = 1): own point j at ext position e, global index x. */
+static void rns_end_rhs(const orc_problem* pb, double** g, int e, int64_t x, const double* q,
+                        double* Kq) {
+    const int64_t N = pb->n;
+    const double dx = pb->lx / (double)N;
+    const double gm = pb->gamma;
+    const double kappa = pb->mu * gm / ((gm - 1.0) * pb->pr);
+    const double rhoD = pb->mu / (pb->pr * pb->le);
+    double rho, u, p, T, Y;
+    rns_prims_at(g, e, &rho, &u, &p, &T, &Y);
+    double ux, uxx, Txx, Yxx, conv[4];
+    if (x == 0 || x == N - 1) {
+        /* second-order one-sided differences, inward direction sg */
+        const int sg = x == 0 ? 1 : -1;
+        double f[4][5];   /* points e, e+sg, e+2sg, e+3sg: rho, u, p, T, Y */
+        for (int m = 0; m < 4; ++m)
+            rns_prims_at(g, e + sg * m, &f[m][0], &f[m][1], &f[m][2], &f[m][3], &f[m][4]);
+        double d1v[5], d2v[5];
+        for (int v = 0; v < 5; ++v) {
+            d1v[v] = (double)sg * (-3.0 * f[0][v] + 4.0 * f[1][v] - f[2][v]) / (2.0 * dx);
+            d2v[v] = (2.0 * f[0][v] - 5.0 * f[1][v] + 4.0 * f[2][v] - f[3][v]) / (dx * dx);
+        }
+        const double prim[4] = {rho, u, p, Y};
+        const double dprim[4] = {d1v[0], d1v[1], d1v[2], d1v[4]};
+        orc_lodi(pb, x == 0 ? 0 : 1, 1, prim, dprim, conv);
+        ux = d1v[1];
+        uxx = d2v[1];
+        Txx = d2v[3];
+        Yxx = d2v[4];
+    } else {
+        /* second-order central differences of the conservative fluxes */
+        for (int f = 0; f < 4; ++f) conv[f] = -(g[f][e + 1] - g[f][e - 1]) / (2.0 * dx);
+        ux = (g[4][e + 1] - g[4][e - 1]) / (2.0 * dx);
+        uxx = (g[4][e + 1] - 2.0 * g[4][e] + g[4][e - 1]) / (dx * dx);
+        Txx = (g[5][e + 1] - 2.0 * g[5][e] + g[5][e - 1]) / (dx * dx);
+        Yxx = (g[6][e + 1] - 2.0 * g[6][e] + g[6][e - 1]) / (dx * dx);
+    }
+    Kq[0] = conv[0];
+    Kq[1] = conv[1] + (4.0 / 3.0) * pb->mu * uxx;
+    Kq[2] = conv[2] + (4.0 / 3.0) * pb->mu * (ux * ux + u * uxx) + kappa * Txx + pb->q * rhoD * Yxx;
+    Kq[3] = conv[3] + rhoD * Yxx + arrhenius(pb, q);
+}
+
+/* lo: global index of own point 0 (for the non-periodic ends) */
+static void rhs_region(const orc_problem* pb, int64_t lo, int64_t np, double** g, const double* lam,
                        double** vown, double** K, double* flux) {
     const int F = orc_nfields(pb->pde);
     const int H = orc_halo_width(pb->scheme);
@@ -333,6 +435,13 @@ static void rhs_region(const orc_problem* pb, int64_t np, double** g, const doub
             int e = (int)(j + H);
             double q[MAXF];
             for (int f = 0; f < F; ++f) q[f] = vown[f][j];
+            const int64_t x = lo + j;
+            if (pb->bc == 1 && (x < H || x >= pb->n - H)) {
+                double Kq[4];
+                rns_end_rhs(pb, g, e, x, q, Kq);
+                for (int f = 0; f < 4; ++f) K[f][j] = Kq[f];
+                continue;
+            }
             double rho, u, T, Y;
             reactive_primitives(pb, q, &rho, &u, &T, &Y);
             double dC0 = d1(g[0], e, H, c1, dx), dC1 = d1(g[1], e, H, c1, dx);
@@ -384,6 +493,12 @@ static int validate(const orc_problem* pb) {
     case ORC_PDE_REACTIVE_NS:
         if (weno) return ORC_EINVAL;
         break;
+    }
+    if (pb->bc != 0 && pb->bc != 1) return ORC_EINVAL;
+    if (pb->bc == 1) {
+        /* the end closure reads four points inside the first and the last PE */
+        if (pb->pde != ORC_PDE_REACTIVE_NS) return ORC_EINVAL;
+        if ((1 * pb->n) / pb->p < 4 || pb->n - ((int64_t)(pb->p - 1) * pb->n) / pb->p < 4) return ORC_EINVAL;
     }
     return ORC_OK;
 }
@@ -453,7 +568,7 @@ static void rhs_sync_field(const orc_run* r, const double* X, double* out) {
         vown[f] = (double*)X + (int64_t)f * N;
         K[f] = out + (int64_t)f * N;
     }
-    rhs_region(&r->pb, N, g, lam, vown, K, NULL);
+    rhs_region(&r->pb, 0, N, g, lam, vown, K, NULL);
 }
 
 /* Fill the synchronous stage cache G[m][1..S-1] from G[m][0] = u^m. */
@@ -521,7 +636,7 @@ static void rhs_pe(orc_run* r, int64_t p, int s, const double* V, double* Kout) 
         K[f] = kbuf + (int64_t)f * np;
         for (int64_t j = 0; j < np; ++j) vown[f][j] = V[(int64_t)f * N + lo + j];
     }
-    rhs_region(&r->pb, np, g, lam, vown, K,
+    rhs_region(&r->pb, lo, np, g, lam, vown, K,
                is_weno(&r->pb) ? r->flux + (lo + p) * F : NULL);
     for (int f = 0; f < F; ++f)
         for (int64_t j = 0; j < np; ++j) Kout[(int64_t)f * N + lo + j] = K[f][j];

@@ -23,6 +23,13 @@
  *     atRecon / atReconR / atReconRm / atReconM / beta2AT* (J = 2).
  *   - AS mode: standard schemes used with the delayed level (J = 1, eq.
  *     async-fde, eq. asweno).  SYNC mode: the plain periodic scheme.
+ *   - non-periodic ends (bc = 1, the acoustic-wave case of Sec. 5.1 and the
+ *     boundary remarks of Sec. 6): second-order central differences at the
+ *     points closer to an end than the interior stencil reaches, second-order
+ *     one-sided differences at the two end points, where the convective terms
+ *     take the characteristic (LODI) form of the non-reflecting conditions the
+ *     paper cites (Thompson 1987; Poinsot & Lele 1992) with the incoming wave
+ *     amplitudes set to zero.  The ends are not PE boundaries: no delays.
  *
  * Errors: every int-returning function returns ORC_OK (0) or a negative code.
  * Ownership: the caller owns every pointer it passes; the run owns its own
@@ -51,7 +58,8 @@ typedef struct orc_problem {
     int32_t p;            /* number of PEs, 1 <= P <= N                         */
     int32_t n_cdf;        /* 0: uniform on {0..kmax}; else == kmax               */
     int32_t at_levels;    /* J, time levels of the AT extrapolation; 0: default  */
-    int32_t pad0;
+    int32_t bc;           /* 0: periodic; 1: two physical ends with non-reflecting
+                             characteristic conditions (reactive NS, central FD)  */
     uint64_t cdf[16];     /* cumulative thresholds on a 2^32 scale               */
     double x0, lx, dt;
     double c, alpha, r, gamma, q, ea, b, mu, pr, le, weno_eps;
@@ -82,6 +90,11 @@ uint64_t orc_mix64(uint64_t z);
 int  orc_draw(const orc_problem* pb, int64_t step, int64_t idx, int side);
 int  orc_extrap_weights(int J, int k, double* w);
 int  orc_rhs_sync(const orc_problem* pb, const double* q, double* out);
+/* Convective time derivatives of (rho, rho u, rho E, rho Y) at an end point in the
+ * characteristic (LODI) form, from the primitives (rho, u, p, Y) and their x
+ * derivatives; side 0 left, 1 right; drop = 1 sets the incoming amplitudes to 0. */
+int  orc_lodi(const orc_problem* pb, int side, int drop, const double* prim, const double* dprim,
+              double* out);
 int  orc_nfields(int pde);
 int  orc_halo_width(int scheme);
 int  orc_levels(int scheme, int mode, int at_levels);
