@@ -81,10 +81,18 @@ enum at_precision { AT_FP64 = 0, AT_FP32C = 1, AT_FP32 = 2 };
  *   weno_eps     epsilon of the WENO weights (eq. omg), e.g. 1e-6.
  *   seed, problem_id  key of the counter-based delay generator (SplitMix64
  *                finaliser; draw for (step, pe, side) as in the oracle docs).
+ *   bc           0: periodic.  1: two physical ends with non-reflecting
+ *                characteristic conditions (the acoustic-wave case of Sec. 5.1;
+ *                boundary remarks of Sec. 6): second-order one-sided differences
+ *                and the characteristic (LODI) form of the convective terms with
+ *                the incoming waves removed at the two end points, second-order
+ *                central differences at the other points the interior stencil
+ *                cannot reach.  Reactive NS with central FD only; the first and the
+ *                last PE must hold max(4, S*H) points (AT_EUNSUPPORTED otherwise).
  */
 typedef struct at_problem_desc {
     int32_t pde, scheme, mode, rk, granularity, precision;
-    int32_t kmax, at_levels, n_cdf, pad0;
+    int32_t kmax, at_levels, n_cdf, bc;
     int64_t n;
     int32_t p, pad1;
     uint64_t cdf[16];

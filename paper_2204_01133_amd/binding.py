@@ -23,6 +23,7 @@ MODE_IDS = {"sync": 0, "as": 1, "at": 2}
 RK_IDS = {"fe": 0, "rk2": 1, "ssprk3": 2, "rk4": 3}
 GRAN_IDS = {"per_pe": 0, "per_pe_side": 1, "per_boundary": 2}
 PREC_IDS = {"fp64": 0, "fp32c": 1, "fp32": 2}
+BC_IDS = {"periodic": 0, "nscbc": 1}
 
 AT_OK, AT_EINVAL, AT_EUNSUPPORTED, AT_ESTATE, AT_EHIP, AT_ESTALE, AT_ERANGE = 0, -1, -2, -3, -4, -5, -6
 Q_STEP, Q_NUM_TILES, Q_NUM_GROUPS, Q_TOTAL_POINTS, Q_STATE_BYTES, Q_STAGES, Q_LDS_BYTES, \
@@ -34,7 +35,7 @@ class AtProblemDesc(ctypes.Structure):
         ("pde", ctypes.c_int32), ("scheme", ctypes.c_int32), ("mode", ctypes.c_int32),
         ("rk", ctypes.c_int32), ("granularity", ctypes.c_int32), ("precision", ctypes.c_int32),
         ("kmax", ctypes.c_int32), ("at_levels", ctypes.c_int32), ("n_cdf", ctypes.c_int32),
-        ("pad0", ctypes.c_int32),
+        ("bc", ctypes.c_int32),
         ("n", ctypes.c_int64), ("p", ctypes.c_int32), ("pad1", ctypes.c_int32),
         ("cdf", ctypes.c_uint64 * 16),
         ("x0", ctypes.c_double), ("lx", ctypes.c_double), ("dt", ctypes.c_double),
@@ -74,6 +75,7 @@ def describe(pr) -> AtProblemDesc:
     d.kmax = pr.kmax
     d.at_levels = pr.at_levels
     d.n_cdf = len(pr.cdf)
+    d.bc = BC_IDS[getattr(pr, "bc", "periodic")]
     for i, v in enumerate(pr.cdf):
         d.cdf[i] = int(v)
     d.n = pr.n

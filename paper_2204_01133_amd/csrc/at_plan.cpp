@@ -126,6 +126,7 @@ static int validate(const at_problem_desc& d, int idx, std::string& err) {
     }
     if (d.at_levels < 0 || d.at_levels > 6) return bad("at_levels must be in 0..6");
     if (!(d.dt > 0.0) || !(d.lx > 0.0)) return bad("dt and lx must be positive");
+    if (d.bc != 0 && d.bc != 1) return bad("unknown bc");
     return AT_OK;
 }
 
@@ -186,6 +187,21 @@ int make_plan(const at_problem_desc* probs, int n_probs, const at_run_opts* opts
             err = fmt("problem %lld: F x N = %lld state elements exceed the 32-bit offset range", b,
                       (long long)pi.st_elems);
             return AT_EUNSUPPORTED;
+        }
+        if (d.bc == 1) {
+            // non-periodic ends: the reactive NS kind with central differences; the first
+            // and the last PE hold the end closure's four points and the S*H points that
+            // keep the boundary windows of the neighbouring PE boundaries off the ends
+            if (kind != K_RNS) {
+                err = fmt("problem %lld: non-periodic ends need the reactive NS kind", b);
+                return AT_EUNSUPPORTED;
+            }
+            const int64_t need = std::max<int64_t>(4, (int64_t)S * pi.H);
+            const int64_t first = d.n / d.p, last = d.n - ((int64_t)(d.p - 1) * d.n) / d.p;
+            if (first < need || last < need) {
+                err = fmt("problem %lld: non-periodic ends need the first and last PE to hold %lld points", b, need);
+                return AT_EUNSUPPORTED;
+            }
         }
         pi.pe_base = plan.total_pes;
         plan.total_points += d.n;
@@ -396,6 +412,7 @@ void fill_probdev(const Plan& plan, int b, unsigned char* base, ProbDev& P, int6
     P.D = pi.D;
     P.n_cdf = d.n_cdf;
     P.keep_lo = d.precision == AT_FP32C;
+    P.bc = d.bc;
     P.S = pi.S;
     P.F = pi.F;
     for (int i = 0; i < 16; ++i) P.cdf[i] = d.cdf[i];

@@ -155,6 +155,7 @@ struct GView {
 struct ProbDev {
     int64_t n;
     int32_t p, pde, mode, gran, kmax, J, D, n_cdf, keep_lo, S, F;
+    int32_t bc, pad_bc;      // 1: non-periodic ends with non-reflecting conditions
     uint64_t cdf[16];
     uint64_t seed;
     int64_t pid;
@@ -244,6 +245,7 @@ AT_HD AT_FI ProbDev uniform_copy(const AT_CONST ProbDev& P) {
     u.p = uni(P.p); u.pde = uni(P.pde); u.mode = uni(P.mode); u.gran = uni(P.gran);
     u.kmax = uni(P.kmax); u.J = uni(P.J); u.D = uni(P.D); u.n_cdf = uni(P.n_cdf);
     u.keep_lo = uni(P.keep_lo); u.S = uni(P.S); u.F = uni(P.F);
+    u.bc = uni(P.bc);
     u.seed = (uint64_t)uni((int64_t)P.seed);
     u.pid = uni(P.pid);
     u.dt = uni(P.dt); u.inv_dx = uni(P.inv_dx); u.inv_dx2 = uni(P.inv_dx2);
@@ -910,6 +912,80 @@ AT_HD AT_FI void rhs_at(const QV<C>& L, const PhysP& P, int64_t e, const typenam
             if (P.pde == PDE_ADR_LOGISTIC) K[0] += LR(P.r) * (LR)q[0] * (LR(1) - (LR)q[0]);
         }
     }
+}
+
+// ---------------------------------------------------------------------------
+// non-periodic ends (reactive NS kind): the points whose interior stencil would leave
+// the domain.  The two end points take second-order one-sided differences and the
+// characteristic (LODI) form of the convective terms with the incoming waves removed
+// (non-reflecting conditions); the others second-order central differences.  The
+// arithmetic is FP64 in every form.  x: global index of the point, e its ext position;
+// every point read lies inside the domain (the first and the last PE hold at least four).
+// ---------------------------------------------------------------------------
+template <class C>
+AT_HD AT_FI void end_prims(const QV<C>& L, int64_t e, double* v) {
+    // rho, u, p, T, Y from C1 = rho u, C2 = rho u^2 + p, u, T, Y
+    const double u = (double)L.g[4][e], T = (double)L.g[5][e];
+    const double p = (double)L.g[1][e] - (double)L.g[0][e] * u;
+    v[0] = p / T;
+    v[1] = u;
+    v[2] = p;
+    v[3] = T;
+    v[4] = (double)L.g[6][e];
+}
+
+template <class C>
+AT_HD AT_FI void rhs_end_rns(const QV<C>& L, const PhysP& P, int64_t e, int64_t x, int64_t N, const double* q,
+                             typename C::lreal* K) {
+    using LR = typename C::lreal;
+    const double idx = P.inv_dx, idx2 = P.inv_dx2;
+    double cv[4], ux, uxx, Txx, Yxx, uc;
+    if (x == 0 || x == N - 1) {
+        const int sg = x == 0 ? 1 : -1;
+        double f[4][5];
+        for (int m = 0; m < 4; ++m) end_prims<C>(L, e + sg * m, f[m]);
+        double d1v[5], d2v[5];
+        for (int v = 0; v < 5; ++v) {
+            d1v[v] = (double)sg * (4.0 * f[1][v] - 3.0 * f[0][v] - f[2][v]) * (0.5 * idx);
+            d2v[v] = (2.0 * f[0][v] - 5.0 * f[1][v] + 4.0 * f[2][v] - f[3][v]) * idx2;
+        }
+        const double rho = f[0][0], u = f[0][1], p = f[0][2], Y = f[0][4];
+        const double c = sqrt(P.gamma * p / rho);
+        double L1 = (u - c) * (d1v[2] - rho * c * d1v[1]);
+        double L2 = u * (c * c * d1v[0] - d1v[2]);
+        double L3 = u * d1v[4];
+        double L5 = (u + c) * (d1v[2] + rho * c * d1v[1]);
+        // a wave entering the domain (speed > 0 at the left end, < 0 at the right) is removed
+        const double sgn = (double)sg;
+        if (sgn * (u - c) > 0.0) L1 = 0.0;
+        if (sgn * u > 0.0) { L2 = 0.0; L3 = 0.0; }
+        if (sgn * (u + c) > 0.0) L5 = 0.0;
+        const double d1 = (L2 + 0.5 * (L5 + L1)) / (c * c);
+        const double d2 = 0.5 * (L5 + L1);
+        const double d3 = (L5 - L1) / (2.0 * rho * c);
+        cv[0] = -d1;
+        cv[1] = -(u * d1 + rho * d3);
+        cv[3] = -(Y * d1 + rho * L3);
+        cv[2] = -(0.5 * u * u * d1 + d2 / (P.gamma - 1.0) + rho * u * d3) + P.q * cv[3];
+        ux = d1v[1];
+        uxx = d2v[1];
+        Txx = d2v[3];
+        Yxx = d2v[4];
+        uc = u;
+    } else {
+        for (int f = 0; f < 4; ++f) cv[f] = -((double)L.g[f][e + 1] - (double)L.g[f][e - 1]) * (0.5 * idx);
+        const double um = L.g[4][e - 1], u0 = L.g[4][e], up = L.g[4][e + 1];
+        ux = (up - um) * (0.5 * idx);
+        uxx = (up - 2.0 * u0 + um) * idx2;
+        Txx = ((double)L.g[5][e + 1] - 2.0 * (double)L.g[5][e] + (double)L.g[5][e - 1]) * idx2;
+        Yxx = ((double)L.g[6][e + 1] - 2.0 * (double)L.g[6][e] + (double)L.g[6][e - 1]) * idx2;
+        uc = u0;
+    }
+    const double mu43 = (4.0 / 3.0) * P.mu;
+    K[0] = LR(cv[0]);
+    K[1] = LR(cv[1] + mu43 * uxx);
+    K[2] = LR(cv[2] + mu43 * (ux * ux + uc * uxx) + P.kappa * Txx + P.q * P.rhoD * Yxx);
+    K[3] = LR(cv[3] + P.rhoD * Yxx + arrhenius(P, q));
 }
 
 // ---------------------------------------------------------------------------
@@ -1702,7 +1778,19 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const AT_CONST Pr
                         float kk = fmaf(-PP.c0f, lc, ts.khi[k] + lsum);
                         K[0] = fmaf(PP.rlf * u, 1.f - u, kk);
                     } else {
-                        rhs_at<C>(Mc, PP, e, q, K);
+                        const int64_t xg = t.lo + tid + k * nth;
+                        if constexpr (C::KIND == K_RNS) {
+                            if (P.bc == 1 && (xg < H || xg >= N - H)) {
+                                double qd[F];
+#pragma unroll
+                                for (int f = 0; f < F; ++f) qd[f] = (double)q[f];
+                                rhs_end_rns<C>(Mc, PP, e, xg, N, qd, K);
+                            } else {
+                                rhs_at<C>(Mc, PP, e, q, K);
+                            }
+                        } else {
+                            rhs_at<C>(Mc, PP, e, q, K);
+                        }
                     }
 #pragma unroll
                     for (int f = 0; f < F; ++f) {

@@ -29,6 +29,8 @@ def full_length_cases():
         "c5": (W.detonation_c5(), 20),
         "c5batch_min": (prs[int(ns.argmin())], 200),
         "c5batch_max": (prs[int(ns.argmax())], 200),
+        # the acoustic pulse between non-reflecting ends, until it has left the domain
+        "acoustic": (W.acoustic_wave(), W.acoustic_wave().steps),
     }
 
 

@@ -252,7 +252,7 @@ def test_full_c3_sampled(torch, prec):
 @pytest.fixture(scope="module", autouse=True)
 def full_refs(request):
     """Started with the module's first test when any full-length test is selected."""
-    if not any(it.name.startswith("test_full_c") and it.module is request.module
+    if not any(it.name.startswith("test_full_") and it.module is request.module
                for it in request.session.items):
         yield None
         return
@@ -335,6 +335,23 @@ def test_full_c5_batch(torch, full_refs, prec):
     for b in range(0, len(prs), 15):
         u = s.state(b)
         assert np.isfinite(u).all() and u[0].min() > 0.0, b
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32c"])
+def test_full_acoustic_wave(torch, full_refs, prec):
+    """The acoustic pulse between non-reflecting ends (N 512, P 8, FD4 + AT with delays up to
+    2, RK4) over its whole run, until it has left through the right end (1743 steps), graphs
+    of 50 steps: per field against the oracle, delay logs of the first steps bit-exact."""
+    import oracle_jobs
+    pr, steps = oracle_jobs.full_length_cases()["acoustic"]
+    pr = with_precision(pr, prec)
+    s = solver([pr], graph_steps=50, log_steps=steps)
+    s.batch_step(steps)
+    errs = _field_report("acoustic", prec, pr, s.state(0), full_refs.get("acoustic"))
+    assert (errs < tol(prec, pr)).all(), errs
+    d, e = s.delays(0, 0, 8)
+    want = np.array([[[oracle.draw(pr, n, k, 0)] * 2 for k in range(pr.p)] for n in range(8)], dtype=np.uint8)
+    assert np.array_equal(d, want)
 
 
 @pytest.mark.parametrize("prec", ["fp32c", "fp64"])

@@ -100,3 +100,16 @@ def test_uncompiled_combination_rejected():
     with pytest.raises(at_emu.EmuError) as ei:
         _plan([pr])
     assert "-2" in str(ei.value) and "no compiled kernel" in str(ei.value)
+
+
+def test_non_periodic_ends_rules():
+    """Non-periodic ends run on the reactive NS kind only, and need the first and last PE
+    to hold max(4, S*H) points (so that no boundary window reaches an end)."""
+    ok = W.acoustic_wave(n=256, p=8)
+    _plan([ok])
+    with pytest.raises(at_emu.EmuError) as ei:
+        _plan([ok.replace(n=64, p=16, q0=ok.q0[:, :64])])          # 4-point PEs, S*H = 8
+    assert "-2" in str(ei.value)
+    sod = W.euler_sod_c4(n=256, p=4).replace(bc="nscbc")
+    with pytest.raises(at_emu.EmuError):
+        _plan([sod])
