@@ -34,6 +34,9 @@ import numpy as np  # noqa: E402
 import at_workloads as W  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
+# a device copy of 4 GiB (beyond the last-level cache) measured 4782 GB/s read + write on MI355X
+# (profiles/copy_bandwidth.md): the achievable streaming rate, reported beside the peak
+COPY_GBS_MEASURED = 4782.0
 # sources that decide the headline kernel's code and its tiles (the traffic record
 # is used only while their hash matches the one it was measured with)
 KERNEL_SOURCES = ["paper_2204_01133_amd/csrc/at_tile.hpp", "paper_2204_01133_amd/csrc/at_kernels.hpp",
@@ -290,6 +293,7 @@ def run_other(name, steps, warmup, accuracy=True, workers=16):
 
 
 def main():
+    global WARMUP_S
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
@@ -301,9 +305,12 @@ def main():
     ap.add_argument("--config", default="c3", choices=["c3"] + sorted(OTHER_CONFIGS),
                     help="c3 (default): the headline line; others: both forms, timing and accuracy")
     ap.add_argument("--no-accuracy", action="store_true", help="other configurations: timing only")
+    ap.add_argument("--warmup-s", type=float, default=WARMUP_S,
+                    help="seconds of untimed stepping before each timed form (0 for profiler runs)")
     ap.add_argument("--cpu-steps", type=int, default=800,
                     help="steps of the oracle sample timed for cpu_baseline (at least the GPU's)")
     args = ap.parse_args()
+    WARMUP_S = args.warmup_s
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the AT batch shards by "
               "problem across GPUs with no communication (one plan and ring per GPU)", file=sys.stderr)
@@ -412,6 +419,7 @@ def main():
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
+            "frac_of_measured_copy": achieved / COPY_GBS_MEASURED,
             "bytes_per_launch": bytes32["total"],
             "avg_launch_us": t32 / K * 1e6,
             "launches_per_step": launches,
