@@ -16,6 +16,7 @@ the interior stencil cannot reach.
 * Table ap's finding: with delays at PE boundaries, AT stays orders of magnitude closer to
   the synchronous solution than AS, and the AT error grows only slowly with the delay set.
 """
+import json
 import os
 import shutil
 import subprocess
@@ -183,7 +184,9 @@ def test_planted_inflow_at_the_right_end_reflects(tmp_path, monkeypatch):
 # Table ap (Sec. 5.1): L1 error in U against the synchronous run at t = 4e-6 s, AS-SFD and AT,
 # for the delay sets 1-3 of Table dels.  The physical set-up behind it (amplitude, width,
 # grid) is not printed, so the pin takes the ratios, not the values.
-TABLE_AP_L1_U = {"set1": (3.33e-2, 5.88e-5), "set2": (9.87e-2, 6.70e-5), "set3": (8.01e-1, 8.83e-5)}
+_AP = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "table_ap.json")))
+TABLE_AP_L1_U = {c: (_AP["t_4e-6"]["as"]["l1_u"][i], _AP["t_4e-6"]["at"]["l1_u"][i])
+                 for i, c in enumerate(_AP["cases"])}
 
 
 def test_at_error_far_below_as_error_as_in_table_ap():
