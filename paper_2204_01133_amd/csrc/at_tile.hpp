@@ -203,6 +203,10 @@ struct PhysP {
     float c0f;                                     // FP32 scalar kind: sum of lpf and lmf
     float rlf;                                     // FP32 scalar kind: logistic rate (0 without)
     float dtf;                                     // FP32 forms: dt
+    // WENO kinds: eps of the weights in the scaled form of weno5_corr (48/13 eps) and
+    // dx^-1 / 2 (the interface flux is kept without its factor 1/2), FP64 and FP32
+    double epsw, hidx;
+    float epswf, hidxf;
 };
 
 #if defined(__HIP_DEVICE_COMPILE__)
@@ -538,22 +542,82 @@ AT_HD AT_FI double arrhenius(const PhysP& P, const double* q) {
     return -P.b * rho * Y * exp(-P.ea / T);
 }
 
-// WENO5-JS reconstruction at the right edge of v2 (ideal weights 1/10, 3/5, 3/10),
-// nonlinear weights gamma_k/(eps+beta_k)^2 normalised, with the common
-// denominators multiplied out so that one division remains.
+// Reciprocal: the hardware's approximation (1 ulp) in FP32 on the GPU, a division otherwise.
+AT_HD AT_FI double rcp_w(double x) { return 1.0 / x; }
+AT_HD AT_FI float rcp_w(float x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_rcpf(x);
+#else
+    return 1.0f / x;
+#endif
+}
+
+// Euler quantities with one reciprocal of rho: u, the pressure and the wave speed |u| + c
+template <class Q>
+AT_HD AT_FI void euler_uplam(const PhysP& P, const Q* q, Q& u, Q& p, Q& lam) {
+    const Q gm = Q(P.gamma);
+    const Q ir = Q(1) / q[0];
+    u = q[1] * ir;
+    p = (gm - Q(1)) * (q[2] - Q(0.5) * q[1] * u);
+    lam = fabs(u) + sqrt(gm * p * ir);
+}
+
+// reacting Euler quantities of an FP64 state: conserved values g[0..3] (unrounded), fluxes
+// g[4..7] and the wave speed.  FP64 for the reciprocal of rho, u and the pressure (a
+// difference of large energies); the fluxes and the wave speed in the LDS type LR.
+template <class LR, class G>
+AT_HD AT_FI void reul_quant(const PhysP& P, const double* q, G* g, G& lam) {
+    const double ir = 1.0 / q[0];
+    const double u = q[1] * ir;
+    const double p = (P.gamma - 1.0) * (q[2] - P.q * q[3] - 0.5 * q[1] * u);
+    const LR uf = (LR)u, pf = (LR)p, m = (LR)q[1], en = (LR)q[2], ry = (LR)q[3];
+    for (int f = 0; f < 4; ++f) g[f] = (G)q[f];
+    g[4] = (G)q[1];
+    g[5] = (G)(m * uf + pf);
+    g[6] = (G)(uf * (en + pf));
+    g[7] = (G)(ry * uf);
+    lam = (G)(fabs(uf) + sqrt(LR(P.gamma) * (LR)(p * ir)));
+}
+
+// Arrhenius rate -b rho Y exp(-Ea / T) of an FP64 state, T = p / rho
+AT_HD AT_FI double arrhenius_p(const PhysP& P, const double* q) {
+    const double p = (P.gamma - 1.0) * (q[2] - P.q * q[3] - 0.5 * q[1] * q[1] / q[0]);
+    return -P.b * q[3] * exp(-P.ea * q[0] / p);
+}
+
+// WENO5-JS reconstruction at the right edge of the middle value v2 of five (candidate
+// polynomials p_k on the stencils {v_k, v_k+1, v_k+2}, ideal weights 1/10, 3/5, 3/10,
+// nonlinear weights gamma_k / (eps + beta_k)^2 normalised), returned as 6 (vhat - v2).
+// In the differences d_ij = v_j - v_i:
+//   6 p_k - 6 v2 = r_k:  r_0 = 5 d12 - 2 d01,  r_1 = d12 + 2 d23,  r_2 = 4 d23 - d34
+//   beta_k = 13/12 a_k^2 + 1/4 b_k^2 = 13/12 (a_k^2 + 3/13 b_k^2), a_k the second and
+//   b_k the first difference of stencil k:  a = (d12 - d01, d23 - d12, d34 - d23),
+//   b = (3 d12 - d01, d12 + d23, d34 - 3 d23)
+// so that with bh_k = a_k^2 + 3/13 b_k^2 the weights are those of eps at epsh = 12/13 eps.
+// FP32: weights gamma_k / (epsh + bh_k)^2 from reciprocals (no overflow of products of
+// squares); FP64: the weights multiplied by the three denominators, one division.
 template <class R>
-AT_HD AT_FI R weno5(R eps, R v0, R v1, R v2, R v3, R v4) {
-    const R sixth = R(1) / R(6);
-    const R p0 = (R(2) * v0 - R(7) * v1 + R(11) * v2) * sixth;
-    const R p1 = (-v1 + R(5) * v2 + R(2) * v3) * sixth;
-    const R p2 = (R(2) * v2 + R(5) * v3 - v4) * sixth;
-    const R t = R(13) / R(12);
-    const R b0 = t * sq(v0 - R(2) * v1 + v2) + R(0.25) * sq(v0 - R(4) * v1 + R(3) * v2);
-    const R b1 = t * sq(v1 - R(2) * v2 + v3) + R(0.25) * sq(v1 - v3);
-    const R b2 = t * sq(v2 - R(2) * v3 + v4) + R(0.25) * sq(R(3) * v2 - R(4) * v3 + v4);
-    const R d0 = sq(eps + b0), d1 = sq(eps + b1), d2 = sq(eps + b2);
-    const R w0 = R(0.1) * d1 * d2, w1 = R(0.6) * d0 * d2, w2 = R(0.3) * d0 * d1;
-    return (w0 * p0 + w1 * p1 + w2 * p2) / (w0 + w1 + w2);
+AT_HD AT_FI R weno5_corr(R epsh, R v0, R v1, R v2, R v3, R v4) {
+    const R d01 = v1 - v0, d12 = v2 - v1, d23 = v3 - v2, d34 = v4 - v3;
+    const R a0 = d12 - d01, a1 = d23 - d12, a2 = d34 - d23;
+    const R b0 = R(3) * d12 - d01, b1 = d12 + d23, b2 = d34 - R(3) * d23;
+    const R k = R(3.0 / 13.0);
+    const R e0 = epsh + (a0 * a0 + k * (b0 * b0));
+    const R e1 = epsh + (a1 * a1 + k * (b1 * b1));
+    const R e2 = epsh + (a2 * a2 + k * (b2 * b2));
+    const R r0 = R(2) * b0 - d12, r1 = d12 + R(2) * d23, r2 = d23 - b2;
+    R w0, w1, w2;
+    if constexpr (sizeof(R) == 4) {
+        w0 = rcp_w(e0 * e0);
+        w1 = R(6) * rcp_w(e1 * e1);
+        w2 = R(3) * rcp_w(e2 * e2);
+    } else {
+        const R s0 = e0 * e0, s1 = e1 * e1, s2 = e2 * e2;
+        w0 = s1 * s2;
+        w1 = R(6) * (s0 * s2);
+        w2 = R(3) * (s0 * s1);
+    }
+    return (w0 * r0 + w1 * r1 + w2 * r2) * rcp_w(w0 + w1 + w2);
 }
 
 // ---------------------------------------------------------------------------
@@ -697,25 +761,19 @@ AT_HD AT_FI void put_quant(const QV<C>& L, const PhysP& P, int64_t e, const type
             L.lam[e] = (LR)fabs(Q(P.c));
         }
     } else if constexpr (C::KIND == K_EUL) {
-        const Q gm = Q(P.gamma);
-        const Q u = q[1] / q[0];
-        const Q p = (gm - Q(1)) * (q[2] - Q(0.5) * q[1] * u);
+        Q u, p, lam;
+        euler_uplam<Q>(P, q, u, p, lam);
         for (int f = 0; f < 3; ++f) L.g[f][e] = (LR)q[f];
         L.g[3][e] = (LR)q[1];
         L.g[4][e] = (LR)(q[1] * u + p);
         L.g[5][e] = (LR)(u * (q[2] + p));
-        L.lam[e] = (LR)(fabs(u) + sqrt(gm * p / q[0]));
+        L.lam[e] = (LR)lam;
     } else if constexpr (C::KIND == K_REUL) {
         double qd[4] = {(double)q[0], (double)q[1], (double)q[2], (double)q[3]};
-        double rho, u, T, Y;
-        reactive_prims(P, qd, rho, u, T, Y);
-        const double p = rho * T;
-        for (int f = 0; f < 4; ++f) L.g[f][e] = (LR)q[f];
-        L.g[4][e] = (LR)qd[1];
-        L.g[5][e] = (LR)(qd[1] * u + p);
-        L.g[6][e] = (LR)(u * (qd[2] + p));
-        L.g[7][e] = (LR)(qd[3] * u);
-        L.lam[e] = (LR)(fabs(u) + sqrt(P.gamma * T));
+        LR g[8], lam;
+        reul_quant<LR, LR>(P, qd, g, lam);
+        for (int j = 0; j < 8; ++j) L.g[j][e] = g[j];
+        L.lam[e] = lam;
     } else {  // K_RNS
         double qd[4] = {(double)q[0], (double)q[1], (double)q[2], (double)q[3]};
         double rho, u, T, Y;
@@ -744,20 +802,13 @@ AT_HD AT_FI void quant_values(const PhysP& P, const typename C::qreal* q, typena
         if (P.pde == PDE_BURGERS) { g[1] = Q(0.5) * q[0] * q[0]; lam = fabs(q[0]); }
         else { g[1] = Q(P.c) * q[0]; lam = fabs(Q(P.c)); }
     } else if constexpr (C::KIND == K_EUL) {
-        const Q gm = Q(P.gamma);
-        const Q u = q[1] / q[0];
-        const Q p = (gm - Q(1)) * (q[2] - Q(0.5) * q[1] * u);
+        Q u, p;
+        euler_uplam<Q>(P, q, u, p, lam);
         g[0] = q[0]; g[1] = q[1]; g[2] = q[2];
         g[3] = q[1]; g[4] = q[1] * u + p; g[5] = u * (q[2] + p);
-        lam = fabs(u) + sqrt(gm * p / q[0]);
     } else if constexpr (C::KIND == K_REUL) {
         double qd[4] = {(double)q[0], (double)q[1], (double)q[2], (double)q[3]};
-        double rho, u, T, Y;
-        reactive_prims(P, qd, rho, u, T, Y);
-        const double p = rho * T;
-        g[0] = q[0]; g[1] = q[1]; g[2] = q[2]; g[3] = q[3];
-        g[4] = qd[1]; g[5] = qd[1] * u + p; g[6] = u * (qd[2] + p); g[7] = qd[3] * u;
-        lam = fabs(u) + sqrt(P.gamma * T);
+        reul_quant<typename C::lreal, Q>(P, qd, g, lam);
     } else {
         double qd[4] = {(double)q[0], (double)q[1], (double)q[2], (double)q[3]};
         double rho, u, T, Y;
@@ -788,26 +839,36 @@ AT_HD AT_FI typename C::lreal d2(const View<typename C::lreal>& g, int64_t e) {
     return s;
 }
 
-// WENO interface flux between e and e+1 (local Lax-Friedrichs splitting)
+// WENO interface flux between e and e+1 (local Lax-Friedrichs splitting), kept as
+// twice the flux: with v+ = C + al Q on e-2..e+2 and v- = C - al Q on e+3..e-1,
+//   2 F = v+_e + v-_{e+1} + (corr(v+) + corr(v-)) / 6
+// (the split fluxes are (C +- al Q) / 2; their smoothness indicators scale by 4, so the
+// weights take 4 epsh)
 template <class C>
 AT_HD AT_FI void iface_flux(const QV<C>& L, const PhysP& P, int64_t e) {
     using LR = typename C::lreal;
     const LR a0 = L.lam[e], a1 = L.lam[e + 1];
     const LR al = a0 > a1 ? a0 : a1;
-    const LR eps = LR(P.eps);
-    const LR h = LR(0.5);
+    const LR eps = C::F32 ? LR(P.epswf) : LR(P.epsw);
 #pragma unroll
     for (int f = 0; f < C::F; ++f) {
         const View<LR>& Q = L.g[f];
         const View<LR>& Cf = L.g[C::F + f];
-        LR fp[5], fm[5];
+        LR q[6], c[6];
+#pragma unroll
+        for (int m = 0; m < 6; ++m) {
+            q[m] = Q[e - 2 + m];
+            c[m] = Cf[e - 2 + m];
+        }
+        LR vp[5], vm[5];
 #pragma unroll
         for (int m = 0; m < 5; ++m) {
-            fp[m] = h * (Cf[e - 2 + m] + al * Q[e - 2 + m]);
-            fm[m] = h * (Cf[e + 3 - m] - al * Q[e + 3 - m]);
+            vp[m] = c[m] + al * q[m];
+            vm[m] = c[5 - m] - al * q[5 - m];
         }
-        L.flux[f][e] = weno5<LR>(eps, fp[0], fp[1], fp[2], fp[3], fp[4]) +
-                       weno5<LR>(eps, fm[0], fm[1], fm[2], fm[3], fm[4]);
+        const LR cp = weno5_corr<LR>(eps, vp[0], vp[1], vp[2], vp[3], vp[4]);
+        const LR cm = weno5_corr<LR>(eps, vm[0], vm[1], vm[2], vm[3], vm[4]);
+        L.flux[f][e] = (vp[2] + vm[2]) + (cp + cm) * LR(1.0 / 6.0);
     }
 }
 
@@ -901,12 +962,12 @@ AT_HD AT_FI void rhs_at(const QV<C>& L, const PhysP& P, int64_t e, const typenam
                LR(P.q * P.rhoD) * Yxx;
         K[3] = -(d1<C>(L.g[3], e) * idx) + LR(P.rhoD) * Yxx + LR(arrhenius(P, qd));
     } else {  // WENO kinds
-        const LR idx = LR(P.inv_dx);
+        const LR hidx = C::F32 ? LR(P.hidxf) : LR(P.hidx);    // the fluxes are kept doubled
 #pragma unroll
-        for (int f = 0; f < C::F; ++f) K[f] = -((L.flux[f][e] - L.flux[f][e - 1]) * idx);
+        for (int f = 0; f < C::F; ++f) K[f] = -((L.flux[f][e] - L.flux[f][e - 1]) * hidx);
         if constexpr (C::KIND == K_REUL) {
             double qd[4] = {(double)q[0], (double)q[1], (double)q[2], (double)q[3]};
-            K[3] += LR(arrhenius(P, qd));
+            K[3] += LR(arrhenius_p(P, qd));
         }
         if constexpr (C::KIND == K_WSCAL) {
             if (P.pde == PDE_ADR_LOGISTIC) K[0] += LR(P.r) * (LR)q[0] * (LR(1) - (LR)q[0]);
@@ -1043,6 +1104,10 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const AT_CONST Pr
     PP.cf = uni(P.cf); PP.alphaf = uni(P.alphaf); PP.rf = uni(P.rf);
     PP.inv_dxf = uni(P.inv_dxf); PP.inv_dx2f = uni(P.inv_dx2f);
     PP.dtf = uni(P.dtf);
+    PP.epsw = uni(PP.eps * (48.0 / 13.0));
+    PP.hidx = uni(0.5 * PP.inv_dx);
+    PP.epswf = uni((float)PP.epsw);
+    PP.hidxf = uni((float)PP.hidx);
     PP.c0f = uni(P.c0f);
     PP.rlf = uni(P.rlf);
     if constexpr (C::KIND == K_ADR) {
