@@ -220,14 +220,10 @@ int make_plan(const at_problem_desc* probs, int n_probs, const at_run_opts* opts
         VariantKey ks = pi.key, kl = pi.key;
         // default LDS per tile: 6 workgroups per compute unit for the FP32 scalar FD
         // kernels of halo width up to 2 (whose whole-step kernel is held to 6 waves per
-        // SIMD); 64 KiB for the FP32 forms of the Euler WENO kinds, whose registers (about
-        // 160-290 VGPRs) admit 2-3 waves per SIMD anyway, so that a tile packs two of their
-        // 256-point PEs (measured 20-24 % faster on the detonation workloads); 40 KiB, 4
-        // workgroups, for the others
-        const bool weno_f32 = pi.key.f32 && (pi.key.kind == K_EUL || pi.key.kind == K_REUL);
+        // SIMD); 40 KiB, 4 workgroups, for the others (two 256-point PEs of the FP32 WENO
+        // kinds fit: 38 KB for the reacting Euler kind)
         const int64_t lds_budget = plan.opts.lds_budget > 0 ? plan.opts.lds_budget
                                    : (pi.key.kind == K_ADR && pi.key.f32 && pi.key.H <= 2) ? 26 * 1024
-                                   : weno_f32                                              ? 64 * 1024
                                                                                            : 40 * 1024;
         kl.ppt = ppt_large(pi.key.kind, pi.key.f32);
         const int tsmall = BLOCK * ks.ppt, tlarge = BLOCK * kl.ppt;

@@ -354,9 +354,15 @@ struct Cfg {
     // (6 waves), which its default LDS per tile (26 KiB, 6 workgroups per compute unit)
     // matches
     static constexpr int WAVES_STEP = (KIND_ == K_ADR && F32_ && PPT_ == 8 && H_ <= 2) ? 6 : WAVES_PER_EU;
+    // stage parities of the quantity regions: a WENO stage reads the quantities only in its
+    // flux phase (its update phase reads the fluxes), so the next stage's quantities can
+    // overwrite them after the barrier between the two; a central stencil reads them in
+    // the phase that writes the next ones
+    static constexpr int QPAR = WENO ? 1 : 2;
 };
 
 AT_HD AT_FI int64_t align16(int64_t b) { return (b + 15) & ~int64_t(15); }
+AT_HD AT_FI int64_t align256(int64_t b) { return (b + 255) & ~int64_t(255); }
 
 
 constexpr int JMAXW = 8;   // row length of the LDS table of extrapolation weights
@@ -401,22 +407,24 @@ struct Layout {
         // at offset 0 of the launch's LDS, so that the own points' stencil reads take
         // their neighbour offsets as instruction immediates; then the hi parts
         if (C::HILO) { o_glo = o; o += align16(2 * EXM * 4); }
-        o_g = o;     o += align16((C::HILO ? 1 : 2) * C::NQ * EXM * sl);
+        o_g = o;     o += align16((C::HILO ? 1 : C::QPAR) * C::NQ * EXM * sl);
         if (!C::HILO) o_glo = o;
-        o_lam = o;   o += C::WENO ? align16(2 * EXM * sl) : 0;
+        o_lam = o;   o += C::WENO ? align16(C::QPAR * EXM * sl) : 0;
         o_flux = o;  o += C::WENO ? align16(C::F * EXM * sl) : 0;
         if (o < raw_end) o = raw_end;
         // the scalar FD kind's window quantities are its window state (aliased below)
-        o_gw = o;    o += C::KIND == K_ADR ? 0 : align16(2 * C::NQ * EXW * sl);
+        o_gw = o;    o += C::KIND == K_ADR ? 0 : align16(C::QPAR * C::NQ * EXW * sl);
         o_gwlo = o;
-        o_lamw = o;  o += C::WENO ? align16(2 * EXW * sl) : 0;
+        o_lamw = o;  o += C::WENO ? align16(C::QPAR * EXW * sl) : 0;
         o_fluxw = o; o += C::WENO ? align16(C::F * EXW * sl) : 0;
         o_wu = o;    o += align16(C::F * EXW * sl);
         o_wulo = o;  o += C::F32 ? align16(C::F * EXW * 4) : 0;
         o_wq = o;    o += align16(2 * C::F * EXW * sl);
         o_wR = o;    o += rk_keeps_stage_rhs<C::S>() ? align16(SR * C::F * EXW * sl) : 0;
-        o_SO = o;    o += align16(2 * (int64_t)npe_max * SOREC * sl);
-        o_SOhi = o;  o += C::F32 ? align16(2 * (int64_t)npe_max * jl * C::H * C::F * 4) : 0;
+        // the strips of the non-scalar kinds arrive by direct copies of 64 words: whole
+        // 256-byte chunks
+        o_SO = o;    o += align256(2 * (int64_t)npe_max * SOREC * sl);
+        o_SOhi = o;  o += C::F32 ? align256(2 * (int64_t)npe_max * jl * C::H * C::F * 4) : 0;
         o_pelo = o;  o += align16((npe_max + 1) * 4);
         o_keff = o;  o += align16(2 * (int64_t)npe_max * 4);
         o_wt = o;    o += C::KIND == K_ADR ? 0 : align16(16 * JMAXW * 8);   // extrapolation weights [k][l]
@@ -565,11 +573,13 @@ AT_HD AT_FI void euler_uplam(const PhysP& P, const Q* q, Q& u, Q& p, Q& lam) {
 // reacting Euler quantities of an FP64 state: conserved values g[0..3] (unrounded), fluxes
 // g[4..7] and the wave speed.  FP64 for the reciprocal of rho, u and the pressure (a
 // difference of large energies); the fluxes and the wave speed in the LDS type LR.
+// With src, also the Arrhenius rate -b rho Y exp(-Ea / T), T = p / rho, in FP64.
 template <class LR, class G>
-AT_HD AT_FI void reul_quant(const PhysP& P, const double* q, G* g, G& lam) {
+AT_HD AT_FI void reul_quant(const PhysP& P, const double* q, G* g, G& lam, LR* src = nullptr) {
     const double ir = 1.0 / q[0];
     const double u = q[1] * ir;
     const double p = (P.gamma - 1.0) * (q[2] - P.q * q[3] - 0.5 * q[1] * u);
+    if (src) *src = (LR)(-P.b * q[3] * exp(-P.ea / (p * ir)));
     const LR uf = (LR)u, pf = (LR)p, m = (LR)q[1], en = (LR)q[2], ry = (LR)q[3];
     for (int f = 0; f < 4; ++f) g[f] = (G)q[f];
     g[4] = (G)q[1];
@@ -633,6 +643,8 @@ struct TS {
     typename C::lreal K[C::S][C::PPT][C::F];      // stage right-hand sides (each dies after its last use)
     typename C::lreal acc[C::PPT][C::F];          // sum_s b_s K_s so far (s ascending)
     float khi[C::PPT];                            // FP32 scalar kind: hi part of K (fixed in a step)
+    // reacting Euler kind: Arrhenius rate of the stage state, taken where its quantities are
+    typename C::lreal src[C::KIND == K_REUL ? C::PPT : 1];
 };
 
 // views of one set of differentiated quantities (main region or one window parity)
@@ -668,16 +680,16 @@ struct Lds {
         EXM = (int)Lo.EXM; EXW = (int)Lo.EXW; SOREC = (int)Lo.SOREC; jmax = jm;
         const int64_t nm = Lo.EXM, nw = Lo.EXW;
         for (int par = 0; par < 2; ++par) {
-            const int pg = C::HILO ? 0 : par;
+            const int pg = C::HILO ? 0 : par % C::QPAR, pw = par % C::QPAR;
             for (int q = 0; q < C::NQ; ++q) {
                 main[par].g[q] = View<L>{(L*)(base + Lo.o_g) + (pg * C::NQ + q) * nm, nm};
-                win[par].g[q] = View<L>{(L*)(base + Lo.o_gw) + (par * C::NQ + q) * nw, nw};
+                win[par].g[q] = View<L>{(L*)(base + Lo.o_gw) + (pw * C::NQ + q) * nw, nw};
             }
             // interleaved by parity: the lo part of position e is element 2e of the view
             main[par].glo = View<float>{(float*)(base + Lo.o_glo) + par, C::HILO ? 2 * nm - par : 0};
-            main[par].lam = View<L>{(L*)(base + Lo.o_lam) + par * nm, C::WENO ? nm : 0};
+            main[par].lam = View<L>{(L*)(base + Lo.o_lam) + pw * nm, C::WENO ? nm : 0};
             win[par].glo = View<float>{(float*)(base + Lo.o_gwlo) + par * nw, C::HILO ? nw : 0};
-            win[par].lam = View<L>{(L*)(base + Lo.o_lamw) + par * nw, C::WENO ? nw : 0};
+            win[par].lam = View<L>{(L*)(base + Lo.o_lamw) + pw * nw, C::WENO ? nw : 0};
             for (int f = 0; f < C::F; ++f) {
                 main[par].flux[f] = View<L>{(L*)(base + Lo.o_flux) + f * nm, C::WENO ? nm : 0};
                 win[par].flux[f] = View<L>{(L*)(base + Lo.o_fluxw) + f * nw, C::WENO ? nw : 0};
@@ -706,8 +718,9 @@ struct Lds {
             win0 = win[0];
             if constexpr (C::HILO) win0.glo = wulo[0];
         }
-        SO = View<L>{(L*)(base + Lo.o_SO), 2 * (int64_t)npe_max * Lo.SOREC};
-        SOhi = View<float>{(float*)(base + Lo.o_SOhi), C::F32 ? 2 * (int64_t)npe_max * jm * C::H * C::F : 0};
+        // (the padded regions: direct copies write whole 64-word chunks)
+        SO = View<L>{(L*)(base + Lo.o_SO), (Lo.o_SOhi - Lo.o_SO) / (int64_t)sizeof(L)};
+        SOhi = View<float>{(float*)(base + Lo.o_SOhi), C::F32 ? (Lo.o_pelo - Lo.o_SOhi) / 4 : 0};
         pelo = View<int>{(int*)(base + Lo.o_pelo), npe_max + 1};
         keff = View<int>{(int*)(base + Lo.o_keff), 2 * (int64_t)npe_max};
         wt = View<double>{(double*)(base + Lo.o_wt), C::KIND == K_ADR ? 0 : 16 * JMAXW};
@@ -745,8 +758,10 @@ AT_HD AT_FI int64_t wrapi(int64_t x, int64_t n) {
 // quantities: differentiated values written at an ext position
 // ---------------------------------------------------------------------------
 // q: full state at the point (qreal).  For HILO the caller writes hi/lo itself.
+// src (reacting Euler kind, may be null): receives the Arrhenius rate of the state
 template <class C>
-AT_HD AT_FI void put_quant(const QV<C>& L, const PhysP& P, int64_t e, const typename C::qreal* q) {
+AT_HD AT_FI void put_quant(const QV<C>& L, const PhysP& P, int64_t e, const typename C::qreal* q,
+                           typename C::lreal* src = nullptr) {
     using Q = typename C::qreal;
     using LR = typename C::lreal;
     if constexpr (C::KIND == K_ADR) {
@@ -771,7 +786,7 @@ AT_HD AT_FI void put_quant(const QV<C>& L, const PhysP& P, int64_t e, const type
     } else if constexpr (C::KIND == K_REUL) {
         double qd[4] = {(double)q[0], (double)q[1], (double)q[2], (double)q[3]};
         LR g[8], lam;
-        reul_quant<LR, LR>(P, qd, g, lam);
+        reul_quant<LR, LR>(P, qd, g, lam, src);
         for (int j = 0; j < 8; ++j) L.g[j][e] = g[j];
         L.lam[e] = lam;
     } else {  // K_RNS
@@ -927,9 +942,10 @@ AT_HD AT_FI float hilo_lo_sum(const View<float>& lo2, uint32_t eb, int par, cons
     return k;
 }
 
+// src (reacting Euler kind, may be null): the Arrhenius rate of q, taken with its quantities
 template <class C>
 AT_HD AT_FI void rhs_at(const QV<C>& L, const PhysP& P, int64_t e, const typename C::qreal* q,
-                        typename C::lreal* K) {
+                        typename C::lreal* K, const typename C::lreal* src = nullptr) {
     using LR = typename C::lreal;
     if constexpr (C::KIND == K_ADR) {
         // -c u_x + alpha u_xx as one central stencil on differences to the centre
@@ -966,8 +982,12 @@ AT_HD AT_FI void rhs_at(const QV<C>& L, const PhysP& P, int64_t e, const typenam
 #pragma unroll
         for (int f = 0; f < C::F; ++f) K[f] = -((L.flux[f][e] - L.flux[f][e - 1]) * hidx);
         if constexpr (C::KIND == K_REUL) {
-            double qd[4] = {(double)q[0], (double)q[1], (double)q[2], (double)q[3]};
-            K[3] += LR(arrhenius_p(P, qd));
+            if (src) {
+                K[3] += *src;
+            } else {
+                double qd[4] = {(double)q[0], (double)q[1], (double)q[2], (double)q[3]};
+                K[3] += LR(arrhenius_p(P, qd));
+            }
         }
         if constexpr (C::KIND == K_WSCAL) {
             if (P.pde == PDE_ADR_LOGISTIC) K[0] += LR(P.r) * (LR)q[0] * (LR(1) - (LR)q[0]);
@@ -1284,13 +1304,40 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const AT_CONST Pr
             }
         }
     };
-    auto ring_put = [&](int side_idx, int l, const LR (&v)[nrec], const float (&vh)[nhi]) {
-        const int sob = side_idx * L.SOREC + l * nrec;
-#pragma unroll
-        for (int r = 0; r < nrec; ++r) L.SO[sob + r] = v[r];
+    // the delayed strips of every PE side and level (non-scalar kinds): word-wise direct
+    // copies of wave-sized chunks of consecutive LDS words, the lo parts (FP64: the
+    // values) into SO [side][level][word], the FP32 hi parts into SOhi [side][level][word].
+    // Each lane takes its PE side's delay from the counter-based draw itself; a level the
+    // side does not read copies the side's nearest record (unused).  Lanes past the end
+    // copy the last word again into the chunk's padding.
+    auto ring_copy = [&](int tid) {
+        const int lane = tid & 63, jm = L.jmax;
+        auto rec_word = [&](int p, int wpl) -> uint32_t {   // ring word of LDS word p
+            const int per_side = jm * wpl;
+            const int side_idx = p / per_side, rem = p - side_idx * per_side;
+            const int l = rem / wpl, r = rem - l * wpl;
+            int kd;
+            const int ke = delays_of(side_idx >> 1, side_idx & 1, kd);
+            const int jeff = ke == 0 ? (first ? 0 : 1) : J;
+            const int lv = l < jeff ? l : 0;
+            return rec_back(ke + lv, side_idx >> 1, side_idx & 1) + (uint32_t)r;
+        };
+        constexpr int wlo = C::F32 ? nrec : 2 * nrec;         // SO words of a level
+        const int nso = 2 * t.npe * jm * wlo;
+        float* const so = (float*)&L.SO[0];
+        for (int c = tid & ~63; c < nso; c += nth) {
+            AT_CHECK((int64_t)(c + 64) * 4 <= L.SO.n * (int64_t)sizeof(LR), "strip copy", c, L.SO.n);
+            const int p = c + lane < nso ? c + lane : nso - 1;
+            lds_copy_word(so + c, lane, ring_f, rec_word(p, wlo) + (C::F32 ? (uint32_t)(H * F) : 0u));
+        }
         if constexpr (C::F32) {
-#pragma unroll
-            for (int r = 0; r < H * F; ++r) L.SOhi[(side_idx * L.jmax + l) * H * F + r] = vh[r];
+            const int nsh = 2 * t.npe * jm * H * F;
+            float* const sh = &L.SOhi[0];
+            for (int c = tid & ~63; c < nsh; c += nth) {
+                AT_CHECK((int64_t)(c + 64) <= L.SOhi.n, "strip copy hi", c, L.SOhi.n);
+                const int p = c + lane < nsh ? c + lane : nsh - 1;
+                lds_copy_word(sh + c, lane, ring_f, rec_word(p, H * F));
+            }
         }
     };
     // FP32 scalar kind: the halo of a PE side at every stage, extrapolated once per step
@@ -1440,15 +1487,20 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const AT_CONST Pr
         }
         const int si0 = first_item(tid, nth, 1);
         const bool has0 = si0 < 2 * t.npe;
-        LR rv[JPR][nrec];
-        float rvh[JPR][nhi];
-        float wl[JPR];
+        // scalar FD kind: the first PE side's levels in registers (extrapolated below);
+        // the other kinds copy the strips straight into LDS
+        constexpr int JR = C::KIND == K_ADR ? JPR : 1;
+        LR rv[JR][nrec];
+        float rvh[JR][nhi];
+        float wl[JR];
         int jeff0 = 0, ke0 = 0;
         if (has0) {
             jeff0 = side_delays(si0, ke0);
+            if constexpr (C::KIND == K_ADR) {
 #pragma unroll
-            for (int l = 0; l < JPF; ++l)
-                if (l < jeff0) ring_ld(si0, ke0, l, rv[l], rvh[l]);
+                for (int l = 0; l < JPF; ++l)
+                    if (l < jeff0) ring_ld(si0, ke0, l, rv[l], rvh[l]);
+            }
             if constexpr (C::HILO) {
 #pragma unroll
                 for (int l = 1; l < JPF; ++l)
@@ -1494,32 +1546,12 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const AT_CONST Pr
                 hq_put64(side_idx, ke, jeff, 1, rv);
             }
         } else {
-            if (has0) {
-#pragma unroll
-                for (int l = 0; l < JPF; ++l)
-                    if (l < jeff0) ring_put(si0, l, rv[l], rvh[l]);
-#pragma unroll
-                for (int l = JPF; l < JM; ++l) {
-                    if (l >= jeff0) continue;
-                    LR v[nrec];
-                    float vh[nhi];
-                    ring_ld(si0, ke0, l, v, vh);
-                    ring_put(si0, l, v, vh);
-                }
-            }
-            // further PE sides (tiles of more than nth / 2 PEs)
+            // delays (and log) of further PE sides (tiles of more than nth / 2 PEs)
             for (int side_idx = si0 + nth; side_idx < 2 * t.npe; side_idx += nth) {
                 int ke;
-                const int jeff = side_delays(side_idx, ke);
-#pragma unroll
-                for (int l = 0; l < JM; ++l) {
-                    if (l >= jeff) continue;
-                    LR v[nrec];
-                    float vh[nhi];
-                    ring_ld(side_idx, ke, l, v, vh);
-                    ring_put(side_idx, l, v, vh);
-                }
+                side_delays(side_idx, ke);
             }
+            ring_copy(tid);
         }
         if (stage_io) {
             const GView<LR> kb{(LR*)P.kbuf, P.kbuf_len};
@@ -1541,7 +1573,7 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const AT_CONST Pr
         }
     });
     // the direct copies complete on the vector-memory counter: drained before the barrier
-    if constexpr (RAW_DMA) rt.sync_mem();
+    if constexpr (RAW_DMA || C::KIND != K_ADR) rt.sync_mem();
     else rt.sync();
 
     // tile-local PE of own point i.  The PE owning global x = lo + i is ceil(z) - 1 with
@@ -1599,7 +1631,7 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const AT_CONST Pr
         else return ts.e[k];
     };
     // quantities of V(s) at own slot k, into the main region of stage parity s & 1
-    auto own_quant = [&](const TS<C>& ts, int k, auto sc) {
+    auto own_quant = [&](TS<C>& ts, int k, auto sc) {
         constexpr int s = decltype(sc)::value;
         const QV<C>& M = L.main[s & 1];
         const int e = pt_e(ts, k);
@@ -1610,6 +1642,8 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const AT_CONST Pr
         if constexpr (C::HILO) {
             if (s == s0) M.g[0][e] = ts.uh[k][0];   // hi: fixed within the step, both parities
             M.glo[2 * (int64_t)e] = vlo[0];
+        } else if constexpr (C::KIND == K_REUL) {
+            put_quant<C>(M, PP, e, q, &ts.src[k]);  // and the source of the stage's right-hand side
         } else {
             put_quant<C>(M, PP, e, q);
         }
@@ -1680,6 +1714,7 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const AT_CONST Pr
         for (int k = 0; k < PPT; ++k) {
             const int i = tid + k * nth;
             if constexpr (!C::HILO) ts.e[k] = -1;
+            if constexpr (C::KIND == K_REUL) ts.src[k] = LR(0);
             // every per-point register gets a value on every path, so that none of them is
             // live across the tile loop (a slot without a point is never read)
             if constexpr (C::HILO) {
@@ -1790,12 +1825,14 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const AT_CONST Pr
 #pragma unroll
                     for (int k = 0; k < PPT; ++k) {
                         const int e = ts.e[k];
-                        if (e < 0) continue;
-                        iface_flux<C>(Mc, PP, e);                  // right interface of the point
-                        // left interface of the PE's first point: its left neighbour is a halo slot
-                        const int i = tid + k * nth;
-                        if (L.pelo[pe_local(i)] == i) iface_flux<C>(Mc, PP, e - 1);
+                        if (k > 0) sched_fence();
+                        if (e >= 0) iface_flux<C>(Mc, PP, e);      // right interface of the point
                     }
+                    // left interface of each PE's first point (its left neighbour is a halo
+                    // slot), as a short work list of its own
+                    sched_fence();
+                    for (int b = first_item(tid, nth, 2 * s + 2); b < t.npe; b += nth)
+                        iface_flux<C>(Mc, PP, L.pelo[b] + 2 * H * b + H - 1);
                 }
                 if (win_active) {
                     const int rlo = (s + 1) * H, rhi = WL - (s + 1) * H;
@@ -1815,7 +1852,7 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const AT_CONST Pr
             if (own_active) {
 #pragma unroll
                 for (int k = 0; k < PPT; ++k) {
-                    if (C::HILO && k % 2 == 0 && k > 0) sched_fence();
+                    if (k > 0 && (C::WENO || (C::HILO && k % 2 == 0))) sched_fence();
                     if (!pt_ok(ts, tid, k)) continue;
                     const int e = pt_e(ts, k);
                     Q q[F];
@@ -1853,6 +1890,8 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const AT_CONST Pr
                             } else {
                                 rhs_at<C>(Mc, PP, e, q, K);
                             }
+                        } else if constexpr (C::KIND == K_REUL) {
+                            rhs_at<C>(Mc, PP, e, q, K, &ts.src[k]);
                         } else {
                             rhs_at<C>(Mc, PP, e, q, K);
                         }
