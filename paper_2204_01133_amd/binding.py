@@ -14,7 +14,7 @@ from typing import List, Optional, Sequence, Tuple
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "_build", "libat.so")
+LIB_PATH = os.path.join(os.environ.get("AT_BUILD_DIR") or os.path.join(_HERE, "_build"), "libat.so")
 
 PDE_IDS = {"adv_diff": 0, "adr_logistic": 1, "burgers": 2, "euler": 3, "reactive_euler": 4,
            "reactive_ns": 5}

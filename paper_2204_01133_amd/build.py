@@ -1,6 +1,10 @@
 """Build libat.so (HIP, gfx950) and the CPU emulation library of its kernels.
 
-    python -m paper_2204_01133_amd.build
+    python -m paper_2204_01133_amd.build [JOBS] [--define NAME=VALUE ...] [--lib-only]
+
+AT_BUILD_DIR (environment) puts the build in another folder (default: _build beside
+this file); the library loader reads the same variable, so that a build with other
+compile-time options (--define, e.g. AT_WENO_DPP=1) can be run side by side.
 
 libat.so: hipcc --offload-arch=gfx950, one object per kernel kind compiled in
 parallel, linked into a shared library with the C ABI of include/at.h.
@@ -18,7 +22,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
-BUILD = os.path.join(HERE, "_build")
+BUILD = os.environ.get("AT_BUILD_DIR") or os.path.join(HERE, "_build")
 LIB = os.path.join(BUILD, "libat.so")
 EMU = os.path.join(BUILD, "libat_emu.so")
 
@@ -60,15 +64,16 @@ def _run(cmd):
     return out
 
 
-def build_lib(jobs: int = 8) -> str:
+def build_lib(jobs: int = 8, defines=()) -> str:
     os.makedirs(BUILD, exist_ok=True)
     stamp = source_hash()
     objs, cmds = [], []
+    dflags = ["-D" + d for d in defines]
     for src in HIP_SOURCES + HOST_SOURCES:
         obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
         objs.append(obj)
         lang = [] if src.endswith(".hip") else ["-x", "c++"]
-        cmds.append([HIPCC] + HIP_FLAGS + lang + ["-c", os.path.join(CSRC, src), "-o", obj])
+        cmds.append([HIPCC] + HIP_FLAGS + dflags + lang + ["-c", os.path.join(CSRC, src), "-o", obj])
     with cf.ThreadPoolExecutor(max_workers=max(1, jobs)) as ex:
         list(ex.map(_run, cmds))
     tmp = LIB + f".tmp{os.getpid()}"
@@ -90,15 +95,23 @@ def build_emu() -> str:
     return EMU
 
 
-def build(jobs: int = 8) -> None:
+def build(jobs: int = 8, defines=(), lib_only: bool = False) -> None:
     with cf.ThreadPoolExecutor(max_workers=2) as ex:
-        f1 = ex.submit(build_lib, jobs)
-        f2 = ex.submit(build_emu)
+        f1 = ex.submit(build_lib, jobs, defines)
+        f2 = None if lib_only else ex.submit(build_emu)
         f1.result()
-        f2.result()
+        if f2 is not None:
+            f2.result()
 
 
 if __name__ == "__main__":
-    build(int(sys.argv[1]) if len(sys.argv) > 1 else 8)
+    import argparse
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("jobs", nargs="?", type=int, default=8)
+    ap.add_argument("--define", action="append", default=[], help="NAME=VALUE for the HIP compile")
+    ap.add_argument("--lib-only", action="store_true", help="skip the CPU emulation library")
+    a = ap.parse_args()
+    build(a.jobs, a.define, a.lib_only)
     print(LIB)
-    print(EMU)
+    if not a.lib_only:
+        print(EMU)

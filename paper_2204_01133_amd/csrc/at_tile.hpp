@@ -854,13 +854,36 @@ AT_HD AT_FI typename C::lreal d2(const View<typename C::lreal>& g, int64_t e) {
     return s;
 }
 
+// Build option: the own points' interface fluxes of the FP32 WENO kinds take the
+// neighbour values from adjacent lanes (DPP wave shifts; lanes hold consecutive points)
+// instead of LDS reads, with LDS reads where a neighbour lies past a wave or PE edge.  Off
+// by default: the shifts are VALU instructions in a VALU-bound phase, and it measured
+// slower than the LDS reads.
+#ifndef AT_WENO_DPP
+#define AT_WENO_DPP 0
+#endif
+#if AT_WENO_DPP && defined(__HIP_DEVICE_COMPILE__)
+constexpr bool WENO_DPP = true;
+__device__ __forceinline__ float lane_prev(float v) {   // the value of lane - 1 (wave_shr:1)
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x138, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float lane_next(float v) {   // the value of lane + 1 (wave_shl:1)
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x130, 0xF, 0xF, false));
+}
+#else
+constexpr bool WENO_DPP = false;
+inline float lane_prev(float v) { return v; }
+inline float lane_next(float v) { return v; }
+#endif
+
 // WENO interface flux between e and e+1 (local Lax-Friedrichs splitting), kept as
 // twice the flux: with v+ = C + al Q on e-2..e+2 and v- = C - al Q on e+3..e-1,
 //   2 F = v+_e + v-_{e+1} + (corr(v+) + corr(v-)) / 6
 // (the split fluxes are (C +- al Q) / 2; their smoothness indicators scale by 4, so the
 // weights take 4 epsh)
-template <class C>
-AT_HD AT_FI void iface_flux(const QV<C>& L, const PhysP& P, int64_t e) {
+// LANES (build option above): the neighbours of an interior point from adjacent lanes.
+template <class C, bool LANES = false>
+AT_HD AT_FI void iface_flux(const QV<C>& L, const PhysP& P, int64_t e, bool interior = false) {
     using LR = typename C::lreal;
     const LR a0 = L.lam[e], a1 = L.lam[e + 1];
     const LR al = a0 > a1 ? a0 : a1;
@@ -870,10 +893,20 @@ AT_HD AT_FI void iface_flux(const QV<C>& L, const PhysP& P, int64_t e) {
         const View<LR>& Q = L.g[f];
         const View<LR>& Cf = L.g[C::F + f];
         LR q[6], c[6];
+        if constexpr (LANES) {   // neighbours e-2..e+3 from lanes -2..+3 (interior points)
+            q[2] = Q[e];
+            c[2] = Cf[e];
+            q[1] = lane_prev(q[2]); q[0] = lane_prev(q[1]);
+            q[3] = lane_next(q[2]); q[4] = lane_next(q[3]); q[5] = lane_next(q[4]);
+            c[1] = lane_prev(c[2]); c[0] = lane_prev(c[1]);
+            c[3] = lane_next(c[2]); c[4] = lane_next(c[3]); c[5] = lane_next(c[4]);
+        }
+        if (!LANES || !interior) {
 #pragma unroll
-        for (int m = 0; m < 6; ++m) {
-            q[m] = Q[e - 2 + m];
-            c[m] = Cf[e - 2 + m];
+            for (int m = 0; m < 6; ++m) {
+                q[m] = Q[e - 2 + m];
+                c[m] = Cf[e - 2 + m];
+            }
         }
         LR vp[5], vm[5];
 #pragma unroll
@@ -1722,10 +1755,17 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const AT_CONST Pr
                 ts.khi[k] = 0.f;
                 ts.acc[k][0] = 0.f;
             }
+            if constexpr (WENO_DPP) ts.eb[k] = 0;
             if (i >= t.npts) continue;
             const int lo = pe_local(i);
             if constexpr (C::HILO) ts.eb[k] = (uint32_t)(i + 2 * H * lo) & 0xFFFFu;
             else ts.e[k] = i + 2 * H * lo + H;
+            if constexpr (WENO_DPP && C::WENO) {
+                // lanes -2..+3 hold points of the same PE (build option)
+                const int lane = tid & 63;
+                ts.eb[k] = lane >= 2 && lane <= 60 && i >= 2 && i + 3 < t.npts && pe_local(i - 2) == lo &&
+                           pe_local(i + 3) == lo;
+            }
             if constexpr (!OWN_REG) {
 #pragma unroll
                 for (int f = 0; f < F; ++f) {
@@ -1826,7 +1866,8 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const AT_CONST Pr
                     for (int k = 0; k < PPT; ++k) {
                         const int e = ts.e[k];
                         if (k > 0) sched_fence();
-                        if (e >= 0) iface_flux<C>(Mc, PP, e);      // right interface of the point
+                        // right interface of the point
+                        if (e >= 0) iface_flux<C, WENO_DPP && C::F32>(Mc, PP, e, ts.eb[k] != 0);
                     }
                     // left interface of each PE's first point (its left neighbour is a halo
                     // slot), as a short work list of its own
