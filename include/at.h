@@ -122,16 +122,24 @@ typedef struct at_problem_desc {
  *                   default of the kernel: 26 KiB, 6 workgroups per compute unit,
  *                   for the FP32 scalar finite-difference kernels of order 2 and 4,
  *                   whose whole-step kernel is held to the registers of 6 waves per
- *                   SIMD; 64 KiB for the FP32 forms of the Euler and reactive Euler
- *                   WENO kernels, whose registers admit only 2-3 waves per SIMD;
- *                   40 KiB, 4 workgroups, otherwise); a tile of one PE may exceed it
- *                   (up to the 160 KiB of a compute unit).
+ *                   SIMD; 40 KiB, 4 workgroups, otherwise); a tile of one PE may
+ *                   exceed it (up to the 160 KiB of a compute unit).
+ *   tile_class      0 = tiles of the small points-per-thread class of the kernel (the
+ *                   default), 1 = every tile of the large class (twice the points per
+ *                   thread, twice the points per tile).
+ *   halo_lds        scalar finite-difference kinds: 0 = the delayed halo strips are
+ *                   loaded into registers and extrapolated in time once per step by
+ *                   one lane per PE side (the default); 1 = they are copied into LDS
+ *                   by every lane and extrapolated where each stage reads them.  The
+ *                   other kinds always copy them into LDS.  The results are the same
+ *                   bit for bit.
  */
 typedef struct at_run_opts {
     int32_t tile_points, persistent, grid_per_cu, graph_steps;
     int32_t xcd_remap, log_steps, override_steps, stage_api;
     int32_t lds_budget;
-    int32_t reserved[7];
+    int32_t tile_class, halo_lds;
+    int32_t reserved[5];
 } at_run_opts;
 
 typedef struct at_ctx at_ctx;

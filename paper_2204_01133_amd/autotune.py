@@ -3,22 +3,28 @@
 For one workload (a list of problems) it times the batched step under candidate
 run options and keeps the fastest.  The options it searches:
 
-- the LDS budget per tile, which sets how many whole PEs a tile packs, the
-  points-per-thread class that follows from the tile size, and how many
-  workgroups share a compute unit;
+- the LDS budget per tile, which sets how many whole PEs a tile packs and how
+  many workgroups share a compute unit, for each points-per-thread class of the
+  kernels (tile_class 0: the small class, 1: the large one, twice the points per
+  thread and per tile);
+- the halo staging of the scalar finite-difference kinds: the delayed strips in
+  registers, extrapolated once per step by one lane per PE side, or staged in LDS
+  by every lane and extrapolated where each stage reads them (halo_lds);
 - the launch shape: one workgroup per tile, or a persistent grid of a few
   workgroups per compute unit striding over the tile list;
 - the tile order: cost order, or consecutive tiles grouped on one XCD.
 
-The search has two stages: the budgets under the default launch shape, then
-the launch shapes and orders under the best budget.  Every candidate computes
-the same result bit for bit (the tiles of a step are independent and every
-point takes the same arithmetic whatever tile holds it); only the time differs.
-A candidate the planner rejects (a PE that does not fit the budget) is skipped.
-Results can be kept in a JSON cache keyed by a signature of the workload and
-the device.
+The search has three stages: the budgets of both tile classes under the default
+launch shape, the halo staging under the best of them (when the workload has a
+scalar finite-difference problem), then the launch shapes and orders.  Every
+candidate computes the same result bit for bit (the tiles of a step are
+independent and every point takes the same arithmetic whatever tile holds it);
+only the time differs.  A candidate the planner rejects (a PE that does not fit
+the budget) is skipped.  Results can be kept in a JSON cache keyed by a
+signature of the workload and the device; ATSolver(..., tuned=CACHE) runs with
+the cached choice.
 
-    python -m paper_2204_01133_amd.autotune --workload c3 [--steps 200]
+    python -m paper_2204_01133_amd.autotune --workload c3 [--steps 200] [--cache tune.json]
 """
 from __future__ import annotations
 
@@ -31,9 +37,14 @@ from typing import Callable, Dict, List, Optional, Sequence
 
 # LDS budgets per tile tried in the first stage (0: the planner's default)
 BUDGETS_KIB = (0, 20, 22, 24, 26, 28, 32, 40, 64, 96, 128, 160)
-# launch shapes and orders tried in the second stage
+# points-per-thread classes tried with every budget
+TILE_CLASSES = (0, 1)
+# launch shapes and orders tried in the last stage
 SHAPES = ({}, {"persistent": 1, "grid_per_cu": 4}, {"persistent": 1, "grid_per_cu": 6},
           {"persistent": 1, "grid_per_cu": 8}, {"xcd_remap": 1})
+
+# problems of the scalar finite-difference kernels (where the halo staging is a choice)
+SCALAR_FD_PDES = ("adv_diff", "adr_logistic")
 
 _SIG_FIELDS = ("pde", "scheme", "mode", "rk", "precision", "n", "p", "kmax", "at_levels", "granularity")
 
@@ -70,6 +81,27 @@ def measure(problems: Sequence, opts: Dict, steps: int = 100, graph_steps: int =
     return ms
 
 
+def _device_name() -> str:
+    try:
+        import torch
+        return torch.cuda.get_device_name(0) if torch.cuda.is_available() else ""
+    except Exception:
+        return ""
+
+
+def cached_opts(problems: Sequence, cache: str, device_name: Optional[str] = None) -> Dict:
+    """The run options the cache holds for this workload on this device (as autotune
+    stored them); raises KeyError when the workload was not tuned (or the library's
+    sources changed since)."""
+    sig = signature(problems, _device_name() if device_name is None else device_name)
+    with open(cache) as fh:
+        stored = json.load(fh)
+    if sig not in stored:
+        raise KeyError(f"no tuned run options for this workload and device in {cache} (signature {sig}); "
+                       "run python -m paper_2204_01133_amd.autotune with --cache")
+    return dict(stored[sig]["opts"])
+
+
 def _key(opts: Dict) -> str:
     return json.dumps(opts, sort_keys=True)
 
@@ -85,11 +117,7 @@ def autotune(problems: Sequence, steps: int = 100, graph_steps: int = 50,
     library's ATError for a candidate the planner rejects."""
     from .binding import ATError
     if device_name is None:
-        try:
-            import torch
-            device_name = torch.cuda.get_device_name(0) if torch.cuda.is_available() else ""
-        except Exception:
-            device_name = ""
+        device_name = _device_name()
     sig = signature(problems, device_name)
     if cache and os.path.exists(cache):
         with open(cache) as fh:
@@ -120,8 +148,12 @@ def autotune(problems: Sequence, steps: int = 100, graph_steps: int = 50,
             raise RuntimeError("no candidate run options were accepted for this workload")
         return min(ok, key=lambda t: (t[0], t[1]))[2]
 
-    budgets = [({} if kib == 0 else {"lds_budget": kib * 1024}) for kib in BUDGETS_KIB]
+    budgets = [dict({} if kib == 0 else {"lds_budget": kib * 1024}, **({"tile_class": 1} if cls else {}))
+               for cls in TILE_CLASSES for kib in BUDGETS_KIB]
     b = best_of(budgets)
+    if any(getattr(p, "scheme", "") in ("fd2", "fd4", "fd8") and getattr(p, "pde", "") in SCALAR_FD_PDES
+           for p in problems):
+        b = best_of([b, dict(b, halo_lds=1)])
     best = best_of([dict(b, **shape) for shape in SHAPES])
     result = {"opts": best, "ms_per_step": seen[_key(best)], "table": table, "signature": sig}
     if cache:

@@ -53,7 +53,8 @@ class AtRunOpts(ctypes.Structure):
         ("grid_per_cu", ctypes.c_int32), ("graph_steps", ctypes.c_int32),
         ("xcd_remap", ctypes.c_int32), ("log_steps", ctypes.c_int32),
         ("override_steps", ctypes.c_int32), ("stage_api", ctypes.c_int32),
-        ("lds_budget", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7),
+        ("lds_budget", ctypes.c_int32), ("tile_class", ctypes.c_int32), ("halo_lds", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 5),
     ]
 
 
@@ -155,14 +156,20 @@ class ATSolver:
     as the level-0 state unless set_state is called).  opts: at_run_opts keys.
     scratch: bind the library's own device scratch (at_bind_scratch) instead of
     a workspace allocated here; for workloads whose workspace fits it.
+    tuned: path of an autotuner cache; the run options it holds for this workload
+    and device are used (opts given here override them).
     """
 
     def __init__(self, problems: Sequence, device: str = "cuda:0", stream=None, set_initial: bool = True,
-                 scratch: bool = False, **opts):
+                 scratch: bool = False, tuned: Optional[str] = None, **opts):
         import torch
 
         if not torch.cuda.is_available():
             raise RuntimeError("ATSolver needs a GPU (HIP device); there is no CPU path")
+        if tuned is not None:
+            from .autotune import cached_opts
+            opts = dict(cached_opts(problems, tuned), **opts)
+        self.run_opts = dict(opts)           # the run options in effect (tuned ones included)
         self.torch = torch
         self.L = load_library()
         self.problems = list(problems)

@@ -112,7 +112,8 @@ KArgs base_args(at_ctx* c, const Group& g) {
     a.npe_max = g.npe_max;
     a.jmax = g.jmax;
     a.lds_bytes = (int32_t)g.lds_bytes;
-    a.flags = (c->plan.opts.log_steps ? KF_LOG : 0) | (c->plan.opts.xcd_remap ? KF_XCD : 0);
+    a.flags = (c->plan.opts.log_steps ? KF_LOG : 0) | (c->plan.opts.xcd_remap ? KF_XCD : 0) |
+              (c->plan.opts.halo_lds ? KF_HALO_LDS : 0);
     return a;
 }
 

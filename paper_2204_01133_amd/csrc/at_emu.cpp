@@ -183,7 +183,7 @@ int emu_step(void* ctx, int n_steps) {
     if (c.stage != 0) return AT_ESTATE;
     try {
         for (int i = 0; i < n_steps; ++i) {
-            const int flags = c.plan.opts.log_steps ? KF_LOG : 0;
+            const int flags = (c.plan.opts.log_steps ? KF_LOG : 0) | (c.plan.opts.halo_lds ? KF_HALO_LDS : 0);
             const int rc = run_all(c, 0, -1, flags);
             if (rc) return rc;
             c.step += 1;
@@ -206,7 +206,7 @@ int emu_rk_stage(void* ctx, int stage) {
     if (!c.plan.opts.stage_api) return AT_ESTATE;
     if (stage != c.stage + 1 || stage < 1 || stage > S) return AT_ESTATE;
     try {
-        int flags = KF_STAGE_IO | (c.plan.opts.log_steps ? KF_LOG : 0);
+        int flags = KF_STAGE_IO | (c.plan.opts.log_steps ? KF_LOG : 0) | (c.plan.opts.halo_lds ? KF_HALO_LDS : 0);
         int rc = run_all(c, stage - 1, stage - 1, flags);
         if (rc) return rc;
     } catch (const std::exception& e) {

@@ -20,13 +20,13 @@ std::string fmt(const char* f, long long a = 0, long long b = 0, long long c = 0
 }  // namespace
 
 bool variant_sizes(const VariantKey& v, int npts_max, int npe_max, int jmax, int64_t* lds_bytes,
-                   int64_t* rec_bytes) {
+                   int64_t* rec_bytes, bool halo_lds) {
 #define AT_SIZE_CASE(K, H_, S_, F32_, PPT_)                                        \
     if (v.kind == (K) && v.H == (H_) && v.S == (S_) && v.f32 == ((F32_) != 0) &&   \
         v.ppt == (PPT_)) {                                                         \
         using C = AT_CFG(K, H_, S_, F32_, PPT_);                                   \
         Layout<C> lo;                                                              \
-        lo.init(npts_max, npe_max, jmax);                                          \
+        lo.init(npts_max, npe_max, jmax, halo_lds);                                \
         *lds_bytes = lo.total;                                                     \
         *rec_bytes = record_bytes<C>();                                            \
         return true;                                                               \
@@ -141,8 +141,9 @@ int make_plan(const at_problem_desc* probs, int n_probs, const at_run_opts* opts
     std::memset(&plan.opts, 0, sizeof(plan.opts));
     if (opts) plan.opts = *opts;
     if (plan.opts.log_steps < 0 || plan.opts.override_steps < 0 || plan.opts.tile_points < 0 ||
-        plan.opts.graph_steps < 0 || plan.opts.grid_per_cu < 0 || plan.opts.lds_budget < 0) {
-        err = "negative option";
+        plan.opts.graph_steps < 0 || plan.opts.grid_per_cu < 0 || plan.opts.lds_budget < 0 ||
+        plan.opts.tile_class < 0 || plan.opts.tile_class > 1 || plan.opts.halo_lds < 0 || plan.opts.halo_lds > 1) {
+        err = "run option out of range";
         return AT_EINVAL;
     }
     plan.info.resize(n_probs);
@@ -159,14 +160,17 @@ int make_plan(const at_problem_desc* probs, int n_probs, const at_run_opts* opts
         rk_tableau(d.rk, &S, a, bw);
         const int kind = kind_of(d.pde, d.scheme);
         const bool f32 = d.precision != AT_FP64;
-        pi.key = VariantKey{kind, halo_of(d.scheme), S, f32, ppt_small(kind, f32)};
+        // tile class 1: every tile takes the large points-per-thread class
+        pi.key = VariantKey{kind, halo_of(d.scheme), S, f32,
+                            plan.opts.tile_class == 1 ? ppt_large(kind, f32) : ppt_small(kind, f32)};
         {
             // both tile classes of the combination must be compiled (e.g. the reactive
             // Navier-Stokes kernels exist for the 4th- and 8th-order stencils only)
             VariantKey kl = pi.key;
             kl.ppt = ppt_large(kind, f32);
             int64_t lds, rec;
-            if (!variant_sizes(pi.key, 1, 1, 1, &lds, &rec) || !variant_sizes(kl, 1, 1, 1, &lds, &rec)) {
+            if (!variant_sizes(pi.key, 1, 1, 1, &lds, &rec, plan.opts.halo_lds != 0) ||
+                !variant_sizes(kl, 1, 1, 1, &lds, &rec, plan.opts.halo_lds != 0)) {
                 err = fmt("problem %lld: no compiled kernel for pde %lld with scheme %lld", b, d.pde, d.scheme);
                 err += fmt(" and %lld RK stages", S);
                 return AT_EUNSUPPORTED;
@@ -249,7 +253,7 @@ int make_plan(const at_problem_desc* probs, int n_probs, const at_run_opts* opts
             bool fits = cur.npe > 0 && cur.npts + np <= pack;
             if (fits) {
                 int64_t lds, rec;
-                fits = variant_sizes(ks, (int)(cur.npts + np), cur.npe + 1, pi.J, &lds, &rec) &&
+                fits = variant_sizes(ks, (int)(cur.npts + np), cur.npe + 1, pi.J, &lds, &rec, plan.opts.halo_lds != 0) &&
                        lds <= lds_budget;
             }
             if (!fits && cur.npe > 0) {
@@ -267,7 +271,7 @@ int make_plan(const at_problem_desc* probs, int n_probs, const at_run_opts* opts
         for (int cls = 0; cls < 2; ++cls)
             for (const Tile& t : (cls ? large[b] : small[b])) {
                 int64_t lds, rec;
-                if (!variant_sizes(cls ? kl : ks, t.npts, t.npe, pi.J, &lds, &rec)) {
+                if (!variant_sizes(cls ? kl : ks, t.npts, t.npe, pi.J, &lds, &rec, plan.opts.halo_lds != 0)) {
                     err = fmt("problem %lld: kernel variant not compiled", b);
                     return AT_EUNSUPPORTED;
                 }
@@ -328,7 +332,7 @@ int make_plan(const at_problem_desc* probs, int n_probs, const at_run_opts* opts
             g.npts_max = std::max(g.npts_max, t.npts);
             g.npe_max = std::max(g.npe_max, t.npe);
             int64_t lds, rec;
-            if (!variant_sizes(g.key, t.npts, t.npe, g.jmax, &lds, &rec)) {   // layouts are per tile
+            if (!variant_sizes(g.key, t.npts, t.npe, g.jmax, &lds, &rec, plan.opts.halo_lds != 0)) {   // layouts are per tile
                 err = "kernel variant not compiled";
                 return AT_EUNSUPPORTED;
             }
@@ -369,7 +373,7 @@ int make_plan(const at_problem_desc* probs, int n_probs, const at_run_opts* opts
             if (d.precision == AT_FP32C) o = align256(o + 4 * (size_t)pi.st_elems);
         }
         int64_t lds;
-        if (!variant_sizes(pi.key, 1, 1, 1, &lds, &pi.rec_bytes)) {
+        if (!variant_sizes(pi.key, 1, 1, 1, &lds, &pi.rec_bytes, plan.opts.halo_lds != 0)) {
             err = fmt("problem %lld: kernel variant not compiled", b);
             return AT_EUNSUPPORTED;
         }

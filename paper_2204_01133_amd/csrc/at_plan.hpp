@@ -27,7 +27,7 @@ struct VariantKey {
 
 // LDS bytes and strip-record bytes of a variant (dispatch over the compiled set).
 bool variant_sizes(const VariantKey& v, int npts_max, int npe_max, int jmax, int64_t* lds_bytes,
-                   int64_t* rec_bytes);
+                   int64_t* rec_bytes, bool halo_lds = false);
 
 struct ProbInfo {
     VariantKey key;           // small-tile variant (ppt_small)

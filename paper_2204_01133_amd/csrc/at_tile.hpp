@@ -190,7 +190,7 @@ struct Tile {
     int64_t lo;              // first global point of the tile
 };
 
-enum KFlags { KF_STAGE_IO = 1, KF_LOG = 2, KF_XCD = 4 };
+enum KFlags { KF_STAGE_IO = 1, KF_LOG = 2, KF_XCD = 4, KF_HALO_LDS = 8 };
 
 // Physics parameters of one problem, hoisted into registers at the start of a
 // tile (uniform across the workgroup: scalar registers on the GPU).
@@ -378,16 +378,17 @@ struct Layout {
     int64_t EXR;   // raw staging range [lo - S*H, lo + npts + S*H)
     int64_t o_g, o_glo, o_lam, o_flux, o_gw, o_gwlo, o_lamw, o_fluxw, o_wu, o_wulo, o_wq, o_wR,
         o_SO, o_SOhi, o_pelo, o_keff, o_wt, o_rh, o_rl, total;
-    AT_HD void init(int npts_max, int npe_max, int jmax) {
+    // halo_lds: the scalar FD kind stages the delayed strips of every level in LDS
+    AT_HD void init(int npts_max, int npe_max, int jmax, bool halo_lds = false) {
         using L = typename C::lreal;
         const int64_t sl = (int64_t)sizeof(L);
         EXM = npts_max + 2 * C::H * (int64_t)npe_max;
         NW = npe_max + 1;
         EXW = NW * C::WL;
         if (C::HILO) EXW = (EXW + 63) & ~int64_t(63);   // whole wave-sized chunks (direct copy)
-        // per PE side: the delayed strips of jmax levels, or (scalar FD kind) their
-        // extrapolation to level n, one level's worth
-        const int64_t jl = C::KIND == K_ADR ? 1 : jmax;
+        // per PE side: the delayed strips of jmax levels, or (scalar FD kind with the
+        // strips in registers) their extrapolation to level n, one level's worth
+        const int64_t jl = C::KIND == K_ADR && !halo_lds ? 1 : jmax;
         SOREC = jl * C::S * C::H * C::F;
         // FP32 scalar kind: no raw range (own points go to registers, windows straight
         // into the window region)
@@ -675,8 +676,8 @@ struct Lds {
     View<L> rh[C::F];          // raw u^n (FP64 value / FP32 hi) on [lo - S*H, lo + npts + S*H)
     View<float> rl[C::F];      // raw FP32 lo
     int EXM, EXW, SOREC, jmax;
-    AT_HD void init(unsigned char* base, const Layout<C>& Lo, int npe_max, int jm) {
-        if (C::KIND == K_ADR) jm = 1;    // one extrapolated level per side
+    AT_HD void init(unsigned char* base, const Layout<C>& Lo, int npe_max, int jm, bool halo_lds = false) {
+        if (C::KIND == K_ADR && !halo_lds) jm = 1;    // one extrapolated level per side
         EXM = (int)Lo.EXM; EXW = (int)Lo.EXW; SOREC = (int)Lo.SOREC; jmax = jm;
         const int64_t nm = Lo.EXM, nw = Lo.EXW;
         for (int par = 0; par < 2; ++par) {
@@ -1177,11 +1178,13 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const AT_CONST Pr
     using TB = RKTab<S>;
 
     // LDS layout sized by this tile (the launch allocates the largest over its tiles)
+    // scalar FD kind: the delayed strips staged in LDS (run option) instead of registers
+    const bool staged = C::KIND == K_ADR && (a.flags & KF_HALO_LDS) != 0;
     Layout<C> Lo;
-    Lo.init(t.npts, t.npe, a.jmax);
+    Lo.init(t.npts, t.npe, a.jmax, staged);
     AT_CHECK(Lo.total <= a.lds_bytes, "tile LDS", Lo.total, a.lds_bytes);
     Lds<C> L;
-    L.init(lds_base, Lo, t.npe, a.jmax);
+    L.init(lds_base, Lo, t.npe, a.jmax, staged);
 
 
     const int nth = rt.nthreads();
@@ -1530,9 +1533,11 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const AT_CONST Pr
         if (has0) {
             jeff0 = side_delays(si0, ke0);
             if constexpr (C::KIND == K_ADR) {
+                if (!staged) {
 #pragma unroll
-                for (int l = 0; l < JPF; ++l)
-                    if (l < jeff0) ring_ld(si0, ke0, l, rv[l], rvh[l]);
+                    for (int l = 0; l < JPF; ++l)
+                        if (l < jeff0) ring_ld(si0, ke0, l, rv[l], rvh[l]);
+                }
             }
             if constexpr (C::HILO) {
 #pragma unroll
@@ -1558,7 +1563,14 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const AT_CONST Pr
                 }
             }
         }
-        if constexpr (C::HILO) {
+        if (staged) {
+            // scalar FD kind, strips staged in LDS: delays of further PE sides, then the copies
+            for (int side_idx = si0 + nth; side_idx < 2 * t.npe; side_idx += nth) {
+                int ke;
+                side_delays(side_idx, ke);
+            }
+            ring_copy(tid);
+        } else if constexpr (C::HILO) {
             if (has0 && jeff0 > 0) hq_put(si0, ke0, jeff0, JPF, rv, rvh, wl);
             // further PE sides (tiles of more than nth / 2 PEs)
             for (int side_idx = si0 + nth; side_idx < 2 * t.npe; side_idx += nth) {
@@ -1694,7 +1706,36 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const AT_CONST Pr
         const QV<C>& M = L.main[s & 1];
         const int e = halo_e(side_idx >> 1, side_idx & 1, h);
         const int sob = side_idx * L.SOREC;
-        if constexpr (C::HILO) {
+        if (C::KIND == K_ADR && staged) {
+            // the staged levels, extrapolated here as the load phase does it with the
+            // strips in registers (same operations, same order)
+            const int ke = L.keff[side_idx];
+            const int jeff = ke == 0 ? 1 : J;
+            const int hb = side_idx * L.jmax * H * F;       // FP32 hi words of level 0
+            const int wofs = (s * H + h) * F;               // the stage's word in a level
+            if constexpr (C::HILO) {
+                const float hi0 = L.SOhi[hb + h * F];
+                const float lo0 = L.SO[sob + wofs];
+                float lo = lo0;
+#pragma unroll
+                for (int l = 1; l < JM; ++l) {
+                    if (l >= jeff) continue;
+                    const float w = (float)WTAB.w[J][ke][l];
+                    lo += w * ((L.SOhi[hb + l * H * F + h * F] - hi0) + (L.SO[sob + l * S * H * F + wofs] - lo0));
+                }
+                if (s == s0) M.g[0][e] = hi0;
+                M.glo[2 * (int64_t)e] = lo;
+            } else {
+                const int kw = ke == 0 ? 1 : J;
+                LR acc = LR(WTAB.w[kw][ke][0]) * L.SO[sob + wofs];
+#pragma unroll
+                for (int l = 1; l < JM; ++l) {
+                    if (l >= jeff) continue;
+                    acc += LR(WTAB.w[kw][ke][l]) * L.SO[sob + l * S * H * F + wofs];
+                }
+                M.g[0][e] = acc;
+            }
+        } else if constexpr (C::HILO) {
             // extrapolated in the load phase
             if (s == s0) M.g[0][e] = L.SOhi[side_idx * H * F + h * F];
             M.glo[2 * (int64_t)e] = L.SO[sob + (s * H + h) * F];
@@ -1753,7 +1794,8 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const AT_CONST Pr
             if constexpr (C::HILO) {
                 ts.eb[k] = 0;
                 ts.khi[k] = 0.f;
-                ts.acc[k][0] = 0.f;
+                // (the per-stage entry point has loaded sum_{s<s0} b_s K_s already)
+                if (!stage_io) ts.acc[k][0] = 0.f;
             }
             if constexpr (WENO_DPP) ts.eb[k] = 0;
             if (i >= t.npts) continue;

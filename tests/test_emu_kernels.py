@@ -57,8 +57,12 @@ def test_emu_mixed_kinds_one_context():
 
 
 @pytest.mark.parametrize("make", [lambda: W.adv_diff_c1(n=256, p=8, kmax=3),
+                                  lambda: W.adv_diff_c1(n=256, p=8, kmax=3, precision="fp32c"),
+                                  lambda: W.adv_diff_c1(n=250, p=7, kmax=2, rk="rk2", precision="fp32"),
                                   lambda: W.euler_sod_c4(n=256, p=8),
-                                  lambda: W.reactive_ns_c2(n=256, p=4)])
+                                  lambda: W.euler_sod_c4(n=256, p=8, precision="fp32c"),
+                                  lambda: W.reactive_ns_c2(n=256, p=4),
+                                  lambda: W.reactive_ns_c2(n=256, p=4, precision="fp32c")])
 def test_emu_per_stage_equals_fused(make):
     pr = make()
     a = at_emu.Emu([pr], stage_api=1)
@@ -145,3 +149,29 @@ def test_emu_multi_pe_weno_tiles(prec, make):
     many.step(12)
     assert np.array_equal(one.state(0), many.state(0))
     assert norm_err(pr, many.state(0), _oracle(pr, 12).state()) < tol(prec, pr)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32c"])
+@pytest.mark.parametrize("opts", [{"halo_lds": 1}, {"tile_class": 1}, {"halo_lds": 1, "tile_class": 1}],
+                         ids=["halo_lds", "tile_class", "both"])
+def test_emu_run_options_agree_bitwise(prec, opts):
+    """The halo staging (LDS or registers) and the tile class change where the work
+    runs, not its arithmetic: the states equal the default options' bit for bit, in the
+    batched form and in the per-stage form."""
+    prs = [with_precision(p, prec) for p in W.batched_adr_c3(n_problems=6, n_min=256, n_max=2048, steps=20)]
+    prs.append(with_precision(W.adv_diff_c1(n=250, p=7, kmax=3, scheme="fd8"), prec).replace(problem_id=99))
+    steps = 17
+    ref = at_emu.Emu(prs)
+    got = at_emu.Emu(prs, **opts)
+    ref.step(steps)
+    got.step(steps)
+    for b in range(len(prs)):
+        assert np.array_equal(ref.state(b), got.state(b)), b
+    pr = with_precision(W.adv_diff_c1(n=256, p=8, kmax=3), prec)
+    a = at_emu.Emu([pr], stage_api=1)
+    c = at_emu.Emu([pr], stage_api=1, **opts)
+    for _ in range(5):
+        a.step(1)
+        for s in range(1, 5):
+            c.rk_stage(s)
+    assert np.array_equal(a.state(0), c.state(0))

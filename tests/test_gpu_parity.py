@@ -84,7 +84,9 @@ def test_launch_forms_agree_bitwise(torch, prec):
     ref = _run(prs, steps, "step")                                     # plain per problem
     variants = [("batch_step", {}), ("batch_step", {"persistent": 1, "grid_per_cu": 1}),
                 ("batch_step", {"xcd_remap": 1}), ("batch_step", {"graph_steps": 4}),
-                ("batch_step", {"graph_steps": 5, "persistent": 1})]
+                ("batch_step", {"graph_steps": 5, "persistent": 1}), ("batch_step", {"halo_lds": 1}),
+                ("batch_step", {"tile_class": 1}), ("step", {"halo_lds": 1, "tile_class": 1}),
+                ("batch_step", {"halo_lds": 1, "graph_steps": 4, "persistent": 1})]
     for method, opts in variants:
         got = _run(prs, steps, method, **opts)
         for a, b in zip(got, ref):
@@ -126,6 +128,22 @@ def test_autotuned_options_agree_bitwise(torch):
         assert np.array_equal(a, b), res["opts"]
 
 
+def test_tuned_cache_drives_the_solver(torch, tmp_path):
+    """ATSolver(tuned=cache) runs with the options the autotuner stored for the workload
+    (explicit options override them), with the default options' result bit for bit."""
+    from paper_2204_01133_amd.autotune import autotune
+    prs, _ = batch_case()
+    cache = str(tmp_path / "tune.json")
+    res = autotune(prs, steps=4, graph_steps=2, cache=cache)
+    s = solver(prs, tuned=cache)
+    assert s.run_opts == res["opts"]
+    s.batch_step(13)
+    ref = _run(prs, 13, "batch_step")
+    for b in range(len(prs)):
+        assert np.array_equal(s.state(b), ref[b])
+    assert solver(prs, tuned=cache, persistent=0).run_opts["persistent"] == 0
+
+
 def test_graph_replay_on_torch_stream(torch):
     prs, _ = batch_case()
     st = torch.cuda.Stream()
@@ -140,7 +158,10 @@ def test_graph_replay_on_torch_stream(torch):
 
 
 @pytest.mark.parametrize("make", [lambda: W.adv_diff_c1(n=256, p=8, kmax=3),
+                                  lambda: W.adv_diff_c1(n=256, p=8, kmax=3, precision="fp32c"),
+                                  lambda: W.adv_diff_c1(n=250, p=7, kmax=2, rk="rk2", precision="fp32"),
                                   lambda: W.euler_sod_c4(n=256, p=8),
+                                  lambda: W.euler_sod_c4(n=256, p=8, precision="fp32c"),
                                   lambda: W.reactive_ns_c2(n=256, p=4, precision="fp32c")])
 def test_per_stage_equals_fused(torch, make):
     pr = make()
