@@ -33,7 +33,7 @@ from typing import List, Optional, Sequence, Tuple
 import numpy as np
 
 PDES = ("adv_diff", "adr_logistic", "burgers", "euler", "reactive_euler", "reactive_ns")
-SCHEMES = ("fd2", "fd4", "fd8", "weno5")
+SCHEMES = ("fd2", "fd4", "fd8", "weno5", "weno5i")
 MODES = ("sync", "as", "at")
 RKS = ("fe", "rk2", "ssprk3", "rk4")
 GRANULARITIES = ("per_pe", "per_pe_side", "per_boundary")

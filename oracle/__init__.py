@@ -25,7 +25,7 @@ _lib = None
 
 PDE_IDS = {"adv_diff": 0, "adr_logistic": 1, "burgers": 2, "euler": 3, "reactive_euler": 4,
            "reactive_ns": 5}
-SCHEME_IDS = {"fd2": 0, "fd4": 1, "fd8": 2, "weno5": 3}
+SCHEME_IDS = {"fd2": 0, "fd4": 1, "fd8": 2, "weno5": 3, "weno5i": 4}
 MODE_IDS = {"sync": 0, "as": 1, "at": 2}
 RK_IDS = {"fe": 0, "rk2": 1, "ssprk3": 2, "rk4": 3}
 GRAN_IDS = {"per_pe": 0, "per_pe_side": 1, "per_boundary": 2}
@@ -104,6 +104,8 @@ def load(path: str):
     L.orc_rhs_sync.argtypes = [P(OrcProblem), P(ctypes.c_double), P(ctypes.c_double)]
     L.orc_lodi.argtypes = [P(OrcProblem), ctypes.c_int, ctypes.c_int, P(ctypes.c_double), P(ctypes.c_double),
                            P(ctypes.c_double)]
+    L.orc_weno_interp.argtypes = [ctypes.c_double, P(ctypes.c_double), P(ctypes.c_double)]
+    L.orc_weno_interp.restype = ctypes.c_double
     return L
 
 
@@ -244,6 +246,16 @@ def rhs_sync(pr, q: np.ndarray) -> np.ndarray:
     out = np.empty_like(q)
     _check(lib().orc_rhs_sync(ctypes.byref(s), _dptr(q), _dptr(out)))
     return out
+
+
+def weno_interp(eps: float, v) -> Tuple[float, np.ndarray]:
+    """WENO5 interpolation form: value at the right edge of v[2] from v[0..4], and the
+    three smoothness indicators."""
+    a = np.ascontiguousarray(v, dtype=np.float64)
+    assert a.shape == (5,)
+    beta = np.empty(3)
+    val = lib().orc_weno_interp(float(eps), _dptr(a), _dptr(beta))
+    return float(val), beta
 
 
 def lodi(pr, side: int, drop: bool, prim, dprim) -> np.ndarray:

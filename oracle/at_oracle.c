@@ -72,7 +72,7 @@ int orc_halo_width(int scheme) {
     case ORC_FD2: return 1;
     case ORC_FD4: return 2;
     case ORC_FD8: return 4;
-    case ORC_WENO5: return 3;
+    case ORC_WENO5: case ORC_WENO5I: return 3;
     }
     return -1;
 }
@@ -89,7 +89,7 @@ int orc_levels(int scheme, int mode, int at_levels) {
     case ORC_FD2: return 2;
     case ORC_FD4: return 3;
     case ORC_FD8: return 3;
-    case ORC_WENO5: return 2;
+    case ORC_WENO5: case ORC_WENO5I: return 2;
     }
     return -1;
 }
@@ -147,7 +147,7 @@ int orc_draw(const orc_problem* pb, int64_t step, int64_t idx, int side) {
 /* ------------------------------------------------------------------------- */
 /* Physics: differentiated quantities, wave speed, source.                   */
 /* ------------------------------------------------------------------------- */
-static int is_weno(const orc_problem* pb) { return pb->scheme == ORC_WENO5; }
+static int is_weno(const orc_problem* pb) { return pb->scheme == ORC_WENO5 || pb->scheme == ORC_WENO5I; }
 
 static int nquant(const orc_problem* pb) {
     int F = orc_nfields(pb->pde);
@@ -249,6 +249,38 @@ static double weno5(double eps, double v0, double v1, double v2, double v3, doub
     double a1 = 0.6 / ((eps + b1) * (eps + b1));
     double a2 = 0.3 / ((eps + b2) * (eps + b2));
     return (a0 * p0 + a1 * p1 + a2 * p2) / (a0 + a1 + a2);
+}
+
+/* ------------------------------------------------------------------------- */
+/* WENO5 in interpolation form: the value at the right edge of v2 from the   */
+/* point values v0..v4 (eq. interpS: quadratic interpolants of the three     */
+/* three-point candidates evaluated half a cell right of v2; eq. betaS:      */
+/* smoothness indicators, those of eq. bet1 for the candidate polynomials;   */
+/* eq. omg with the ideal weights 1/16, 5/8, 5/16 of eq. fullSten).          */
+/* ------------------------------------------------------------------------- */
+static double weno5i(double eps, double v0, double v1, double v2, double v3, double v4, double* beta) {
+    double p0 = 3.0 / 8.0 * v0 - 5.0 / 4.0 * v1 + 15.0 / 8.0 * v2;
+    double p1 = -1.0 / 8.0 * v1 + 3.0 / 4.0 * v2 + 3.0 / 8.0 * v3;
+    double p2 = 3.0 / 8.0 * v2 + 3.0 / 4.0 * v3 - 1.0 / 8.0 * v4;
+    double b0 = (4.0 * v0 * v0 + (11.0 * v2 - 19.0 * v1) * v0 + 25.0 * v1 * v1 + 10.0 * v2 * v2
+                 - 31.0 * v1 * v2) / 3.0;
+    double b1 = (4.0 * v1 * v1 + (5.0 * v3 - 13.0 * v2) * v1 + 13.0 * v2 * v2 + 4.0 * v3 * v3
+                 - 13.0 * v2 * v3) / 3.0;
+    double b2 = (10.0 * v2 * v2 + (11.0 * v4 - 31.0 * v3) * v2 + 25.0 * v3 * v3 + 4.0 * v4 * v4
+                 - 19.0 * v3 * v4) / 3.0;
+    double a0 = (1.0 / 16.0) / ((eps + b0) * (eps + b0));
+    double a1 = (5.0 / 8.0) / ((eps + b1) * (eps + b1));
+    double a2 = (5.0 / 16.0) / ((eps + b2) * (eps + b2));
+    if (beta) {
+        beta[0] = b0;
+        beta[1] = b1;
+        beta[2] = b2;
+    }
+    return (a0 * p0 + a1 * p1 + a2 * p2) / (a0 + a1 + a2);
+}
+
+double orc_weno_interp(double eps, const double* v, double* beta) {
+    return weno5i(eps, v[0], v[1], v[2], v[3], v[4], beta);
 }
 
 /* ------------------------------------------------------------------------- */
@@ -405,8 +437,14 @@ static void rhs_region(const orc_problem* pb, int64_t lo, int64_t np, double** g
                     fp[m] = 0.5 * (C[i - 2 + m] + al * Q[i - 2 + m]);
                     fm[m] = 0.5 * (C[i + 3 - m] - al * Q[i + 3 - m]);
                 }
-                double Fp = weno5(pb->weno_eps, fp[0], fp[1], fp[2], fp[3], fp[4]);
-                double Fm = weno5(pb->weno_eps, fm[0], fm[1], fm[2], fm[3], fm[4]);
+                double Fp, Fm;
+                if (pb->scheme == ORC_WENO5I) {     /* interpolation form */
+                    Fp = weno5i(pb->weno_eps, fp[0], fp[1], fp[2], fp[3], fp[4], NULL);
+                    Fm = weno5i(pb->weno_eps, fm[0], fm[1], fm[2], fm[3], fm[4], NULL);
+                } else {
+                    Fp = weno5(pb->weno_eps, fp[0], fp[1], fp[2], fp[3], fp[4]);
+                    Fm = weno5(pb->weno_eps, fm[0], fm[1], fm[2], fm[3], fm[4]);
+                }
                 Fi[ii * F + f] = Fp + Fm;
             }
         }
@@ -482,7 +520,7 @@ static int validate(const orc_problem* pb) {
     if (pb->n_cdf != 0 && pb->n_cdf != pb->kmax) return ORC_EINVAL;
     if (pb->at_levels < 0 || pb->at_levels > MAXJ) return ORC_EINVAL;
     if (!(pb->dt > 0.0) || !(pb->lx > 0.0)) return ORC_EINVAL;
-    int weno = pb->scheme == ORC_WENO5;
+    int weno = is_weno(pb);
     switch (pb->pde) {
     case ORC_PDE_ADV_DIFF: case ORC_PDE_ADR_LOGISTIC:
         if (weno && pb->alpha != 0.0) return ORC_EINVAL;
@@ -817,7 +855,7 @@ int orc_set_override(orc_run* r, int64_t step0, int n_steps, const uint8_t* sche
 }
 
 int orc_get_fluxes(const orc_run* r, int pe, double* out) {
-    if (pe < 0 || pe >= r->pb.p || r->pb.scheme != ORC_WENO5) return ORC_EINVAL;
+    if (pe < 0 || pe >= r->pb.p || !is_weno(&r->pb)) return ORC_EINVAL;
     int64_t lo = pe_lo(r, pe), hi = pe_lo(r, pe + 1);
     memcpy(out, r->flux + (lo + pe) * r->F, sizeof(double) * (size_t)((hi - lo + 1) * r->F));
     return ORC_OK;

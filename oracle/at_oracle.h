@@ -21,6 +21,13 @@
  *     replaced by its Lagrange extrapolation in time from levels n-k~-l,
  *     l = 0..J-1, to level n.  This reproduces Table A (J = 3) and eqs.
  *     atRecon / atReconR / atReconRm / atReconM / beta2AT* (J = 2).
+ *   - WENO5 in interpolation form (Sec. 3, eqs. interpS, fullSten, omg, betaS):
+ *     interface values of the split fluxes interpolated from point values by
+ *     three quadratic candidates with ideal weights 1/16, 5/8, 5/16, then
+ *     differenced as in eq. wender.  The AT form extrapolates the delayed halo
+ *     values in time with two levels (the five-point stochastic stencil of eq.
+ *     stenF, whose candidates are the standard ones applied to the
+ *     extrapolated values).
  *   - AS mode: standard schemes used with the delayed level (J = 1, eq.
  *     async-fde, eq. asweno).  SYNC mode: the plain periodic scheme.
  *   - non-periodic ends (bc = 1, the acoustic-wave case of Sec. 5.1 and the
@@ -47,7 +54,7 @@ enum { ORC_OK = 0, ORC_EINVAL = -1, ORC_ENOMEM = -2, ORC_ESTALE = -3, ORC_ERANGE
 
 enum { ORC_PDE_ADV_DIFF = 0, ORC_PDE_ADR_LOGISTIC = 1, ORC_PDE_BURGERS = 2, ORC_PDE_EULER = 3,
        ORC_PDE_REACTIVE_EULER = 4, ORC_PDE_REACTIVE_NS = 5 };
-enum { ORC_FD2 = 0, ORC_FD4 = 1, ORC_FD8 = 2, ORC_WENO5 = 3 };
+enum { ORC_FD2 = 0, ORC_FD4 = 1, ORC_FD8 = 2, ORC_WENO5 = 3, ORC_WENO5I = 4 };
 enum { ORC_SYNC = 0, ORC_AS = 1, ORC_AT = 2 };
 enum { ORC_FE = 0, ORC_RK2 = 1, ORC_SSPRK3 = 2, ORC_RK4 = 3 };
 enum { ORC_PER_PE = 0, ORC_PER_PE_SIDE = 1, ORC_PER_BOUNDARY = 2 };
@@ -96,6 +103,9 @@ int  orc_rhs_sync(const orc_problem* pb, const double* q, double* out);
 int  orc_lodi(const orc_problem* pb, int side, int drop, const double* prim, const double* dprim,
               double* out);
 int  orc_nfields(int pde);
+/* WENO5 interpolation (eqs. interpS, omg, betaS) of the value at the right edge of v[2]
+ * from v[0..4]; beta (may be null) receives the three smoothness indicators. */
+double orc_weno_interp(double eps, const double* v, double* beta);
 int  orc_halo_width(int scheme);
 int  orc_levels(int scheme, int mode, int at_levels);
 

@@ -54,6 +54,7 @@ def _zero_override(pr, steps):
     lambda: W.adv_diff_c1(n=128, p=8, kmax=3, steps=20),
     lambda: W.batched_adr_c3(n_problems=1, n_min=256, n_max=256)[0].replace(steps=20),
     lambda: W.euler_sod_c4(n=256, p=8, steps=20),
+    lambda: W.euler_sod_c4(n=256, p=8, steps=20).replace(scheme="weno5i"),
     lambda: W.burgers_sweep(64, p=8),
     lambda: W.reactive_ns_c2(n=256, p=8, steps=10),
     lambda: W.detonation_c5(n=512, p=8, steps=10, precision="fp64"),
