@@ -262,12 +262,16 @@ static double weno5i(double eps, double v0, double v1, double v2, double v3, dou
     double p0 = 3.0 / 8.0 * v0 - 5.0 / 4.0 * v1 + 15.0 / 8.0 * v2;
     double p1 = -1.0 / 8.0 * v1 + 3.0 / 4.0 * v2 + 3.0 / 8.0 * v3;
     double p2 = 3.0 / 8.0 * v2 + 3.0 / 4.0 * v3 - 1.0 / 8.0 * v4;
-    double b0 = (4.0 * v0 * v0 + (11.0 * v2 - 19.0 * v1) * v0 + 25.0 * v1 * v1 + 10.0 * v2 * v2
-                 - 31.0 * v1 * v2) / 3.0;
-    double b1 = (4.0 * v1 * v1 + (5.0 * v3 - 13.0 * v2) * v1 + 13.0 * v2 * v2 + 4.0 * v3 * v3
-                 - 13.0 * v2 * v3) / 3.0;
-    double b2 = (10.0 * v2 * v2 + (11.0 * v4 - 31.0 * v3) * v2 + 25.0 * v3 * v3 + 4.0 * v4 * v4
-                 - 19.0 * v3 * v4) / 3.0;
+    /* eq. betaS: the quadratic forms of eq. bet1 for the three candidates, evaluated as
+     * 13/12 (second difference)^2 + 1/4 (first difference)^2, the same forms as the
+     * printed expansion (which loses the small indicators of smooth data to cancellation
+     * when the values are large) */
+    double b0 = 13.0 / 12.0 * (v0 - 2.0 * v1 + v2) * (v0 - 2.0 * v1 + v2)
+              + 0.25 * (v0 - 4.0 * v1 + 3.0 * v2) * (v0 - 4.0 * v1 + 3.0 * v2);
+    double b1 = 13.0 / 12.0 * (v1 - 2.0 * v2 + v3) * (v1 - 2.0 * v2 + v3)
+              + 0.25 * (v1 - v3) * (v1 - v3);
+    double b2 = 13.0 / 12.0 * (v2 - 2.0 * v3 + v4) * (v2 - 2.0 * v3 + v4)
+              + 0.25 * (3.0 * v2 - 4.0 * v3 + v4) * (3.0 * v2 - 4.0 * v3 + v4);
     double a0 = (1.0 / 16.0) / ((eps + b0) * (eps + b0));
     double a1 = (5.0 / 8.0) / ((eps + b1) * (eps + b1));
     double a2 = (5.0 / 16.0) / ((eps + b2) * (eps + b2));
