@@ -47,7 +47,7 @@ enum at_status {
 
 enum at_pde { AT_PDE_ADV_DIFF = 0, AT_PDE_ADR_LOGISTIC = 1, AT_PDE_BURGERS = 2, AT_PDE_EULER = 3,
               AT_PDE_REACTIVE_EULER = 4, AT_PDE_REACTIVE_NS = 5 };
-enum at_scheme { AT_FD2 = 0, AT_FD4 = 1, AT_FD8 = 2, AT_WENO5 = 3 };
+enum at_scheme { AT_FD2 = 0, AT_FD4 = 1, AT_FD8 = 2, AT_WENO5 = 3, AT_WENO5I = 4 };
 enum at_mode { AT_SYNC = 0, AT_AS = 1, AT_AT = 2 };
 enum at_rk { AT_FE = 0, AT_RK2 = 1, AT_SSPRK3 = 2, AT_RK4 = 3 };
 enum at_granularity { AT_PER_PE = 0, AT_PER_PE_SIDE = 1, AT_PER_BOUNDARY = 2 };
@@ -58,6 +58,10 @@ enum at_precision { AT_FP64 = 0, AT_FP32C = 1, AT_FP32 = 2 };
  *   pde/scheme   PDE and spatial scheme; central FD with advection-diffusion(-
  *                logistic) and one-step-chemistry Navier-Stokes, WENO5 with
  *                linear advection (alpha = 0), Burgers, Euler, reactive Euler.
+ *                AT_WENO5 reconstructs the interface fluxes (Jiang-Shu candidates,
+ *                ideal weights 1/10, 3/5, 3/10); AT_WENO5I interpolates them from the
+ *                point values (Sec. 3, eqs. interpS, fullSten: ideal weights 1/16,
+ *                5/8, 5/16; a second-order flux derivative).
  *   mode         AT (extrapolated delayed halos), AS (standard scheme on the
  *                delayed level, eq. async-fde / asweno), SYNC (delay 0).
  *   rk           Butcher tableau: forward Euler, RK2 (eq. rk2), SSP-RK3, RK4.
@@ -70,7 +74,8 @@ enum at_precision { AT_FP64 = 0, AT_FP32C = 1, AT_FP32 = 2 };
  *                n_cdf = kmax: delay k is the number of thresholds cdf[i]
  *                (i < kmax, 2^32 scale) at or below the draw's top 32 bits.
  *   at_levels    J, time levels of the AT extrapolation (0: 3 for FD4/FD8,
- *                2 for FD2 and WENO5).
+ *                2 for FD2 and the WENO schemes; 2 levels make the AT-WENO
+ *                interpolation form the five-point stencil of eq. stenF).
  *   n, p         points and PEs, 1 <= p <= n; PE k owns [floor(kn/p), floor((k+1)n/p)).
  *   x0, lx, dt   grid x_j = x0 + (j + 1/2) lx/n; constant time step.
  *   c, alpha, r  advection speed, diffusivity, logistic rate.

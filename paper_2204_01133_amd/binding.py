@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(os.environ.get("AT_BUILD_DIR") or os.path.join(_HERE, "_
 
 PDE_IDS = {"adv_diff": 0, "adr_logistic": 1, "burgers": 2, "euler": 3, "reactive_euler": 4,
            "reactive_ns": 5}
-SCHEME_IDS = {"fd2": 0, "fd4": 1, "fd8": 2, "weno5": 3}
+SCHEME_IDS = {"fd2": 0, "fd4": 1, "fd8": 2, "weno5": 3, "weno5i": 4}
 MODE_IDS = {"sync": 0, "as": 1, "at": 2}
 RK_IDS = {"fe": 0, "rk2": 1, "ssprk3": 2, "rk4": 3}
 GRAN_IDS = {"per_pe": 0, "per_pe_side": 1, "per_boundary": 2}

@@ -68,7 +68,7 @@ int halo_of(int scheme) {
     case AT_FD2: return 1;
     case AT_FD4: return 2;
     case AT_FD8: return 4;
-    case AT_WENO5: return 3;
+    case AT_WENO5: case AT_WENO5I: return 3;
     }
     return -1;
 }
@@ -82,13 +82,13 @@ int levels_of(int scheme, int mode, int at_levels) {
     switch (scheme) {
     case AT_FD2: return 2;
     case AT_FD4: case AT_FD8: return 3;
-    case AT_WENO5: return 2;
+    case AT_WENO5: case AT_WENO5I: return 2;
     }
     return -1;
 }
 
 int kind_of(int pde, int scheme) {
-    const bool weno = scheme == AT_WENO5;
+    const bool weno = scheme == AT_WENO5 || scheme == AT_WENO5I;
     switch (pde) {
     case AT_PDE_ADV_DIFF: case AT_PDE_ADR_LOGISTIC: return weno ? K_WSCAL : K_ADR;
     case AT_PDE_BURGERS: return weno ? K_WSCAL : -1;
@@ -113,7 +113,7 @@ static int validate(const at_problem_desc& d, int idx, std::string& err) {
     double a[MAXS][MAXS], b[MAXS];
     if (rk_tableau(d.rk, &S, a, b)) return bad("unknown rk");
     if (kind_of(d.pde, d.scheme) < 0) return bad("pde/scheme combination not defined");
-    if ((d.pde == AT_PDE_ADV_DIFF || d.pde == AT_PDE_ADR_LOGISTIC) && d.scheme == AT_WENO5 &&
+    if ((d.pde == AT_PDE_ADV_DIFF || d.pde == AT_PDE_ADR_LOGISTIC) && (d.scheme == AT_WENO5 || d.scheme == AT_WENO5I) &&
         d.alpha != 0.0)
         return bad("WENO5 with diffusion is not defined (alpha must be 0)");
     if (d.n < 1 || d.p < 1 || d.p > d.n) return bad("need 1 <= p <= n");
@@ -413,6 +413,7 @@ void fill_probdev(const Plan& plan, int b, unsigned char* base, ProbDev& P, int6
     P.n_cdf = d.n_cdf;
     P.keep_lo = d.precision == AT_FP32C;
     P.bc = d.bc;
+    P.interp = d.scheme == AT_WENO5I ? 1 : 0;
     P.S = pi.S;
     P.F = pi.F;
     for (int i = 0; i < 16; ++i) P.cdf[i] = d.cdf[i];
@@ -435,7 +436,7 @@ void fill_probdev(const Plan& plan, int b, unsigned char* base, ProbDev& P, int6
     // scalar FD kind: -c d/dx + alpha d2/dx2 as one stencil on differences u_{i+-o} - u_i
     // (the central weights sum to zero), coefficients of o = 1..H
     for (int o = 0; o < 4; ++o) P.lin_p[o] = P.lin_m[o] = 0.0;
-    if (d.scheme != AT_WENO5) {
+    if (d.scheme != AT_WENO5 && d.scheme != AT_WENO5I) {
         const int H = halo_of(d.scheme);
         for (int o = 1; o <= H; ++o) {
             const double a1 = fd_c1(H, o) * P.inv_dx, a2 = fd_c2(H, o) * P.inv_dx2;

@@ -155,7 +155,8 @@ struct GView {
 struct ProbDev {
     int64_t n;
     int32_t p, pde, mode, gran, kmax, J, D, n_cdf, keep_lo, S, F;
-    int32_t bc, pad_bc;      // 1: non-periodic ends with non-reflecting conditions
+    int32_t bc;              // 1: non-periodic ends with non-reflecting conditions
+    int32_t interp;          // WENO kinds: 1 = interpolation form (AT_WENO5I)
     uint64_t cdf[16];
     uint64_t seed;
     int64_t pid;
@@ -196,6 +197,7 @@ enum KFlags { KF_STAGE_IO = 1, KF_LOG = 2, KF_XCD = 4, KF_HALO_LDS = 8 };
 // tile (uniform across the workgroup: scalar registers on the GPU).
 struct PhysP {
     int pde;
+    int interp;           // WENO kinds: interpolation form of the interface values
     double c, alpha, r, gamma, q, ea, b, mu, kappa, rhoD, eps, inv_dx, inv_dx2, dt;
     float cf, alphaf, rf, inv_dxf, inv_dx2f;     // FP32 copies for the FP32 forms
     double lp[4], lm[4];                           // scalar FD kind: combined stencil
@@ -250,6 +252,7 @@ AT_HD AT_FI ProbDev uniform_copy(const AT_CONST ProbDev& P) {
     u.kmax = uni(P.kmax); u.J = uni(P.J); u.D = uni(P.D); u.n_cdf = uni(P.n_cdf);
     u.keep_lo = uni(P.keep_lo); u.S = uni(P.S); u.F = uni(P.F);
     u.bc = uni(P.bc);
+    u.interp = uni(P.interp);
     u.seed = (uint64_t)uni((int64_t)P.seed);
     u.pid = uni(P.pid);
     u.dt = uni(P.dt); u.inv_dx = uni(P.inv_dx); u.inv_dx2 = uni(P.inv_dx2);
@@ -607,7 +610,11 @@ AT_HD AT_FI double arrhenius_p(const PhysP& P, const double* q) {
 // so that with bh_k = a_k^2 + 3/13 b_k^2 the weights are those of eps at epsh = 12/13 eps.
 // FP32: weights gamma_k / (epsh + bh_k)^2 from reciprocals (no overflow of products of
 // squares); FP64: the weights multiplied by the three denominators, one division.
-template <class R>
+// INTERP: the interpolation form (eqs. interpS, fullSten: the candidates' quadratic
+// interpolants of the point values half a cell right of v2, ideal weights 1/16, 5/8, 5/16,
+// the same smoothness indicators), returned as 8 (vhat - v2):
+//   r_0 = 7 d12 - 3 d01,  r_1 = d12 + 3 d23,  r_2 = 5 d23 - d34.
+template <class R, bool INTERP = false>
 AT_HD AT_FI R weno5_corr(R epsh, R v0, R v1, R v2, R v3, R v4) {
     const R d01 = v1 - v0, d12 = v2 - v1, d23 = v3 - v2, d34 = v4 - v3;
     const R a0 = d12 - d01, a1 = d23 - d12, a2 = d34 - d23;
@@ -616,17 +623,28 @@ AT_HD AT_FI R weno5_corr(R epsh, R v0, R v1, R v2, R v3, R v4) {
     const R e0 = epsh + (a0 * a0 + k * (b0 * b0));
     const R e1 = epsh + (a1 * a1 + k * (b1 * b1));
     const R e2 = epsh + (a2 * a2 + k * (b2 * b2));
-    const R r0 = R(2) * b0 - d12, r1 = d12 + R(2) * d23, r2 = d23 - b2;
+    R r0, r1, r2;
+    if constexpr (INTERP) {
+        r0 = R(7) * d12 - R(3) * d01;
+        r1 = d12 + R(3) * d23;
+        r2 = R(5) * d23 - d34;
+    } else {
+        r0 = R(2) * b0 - d12;
+        r1 = d12 + R(2) * d23;
+        r2 = d23 - b2;
+    }
+    // ideal weights in the ratio 1 : 6 : 3 (reconstruction) or 1 : 10 : 5 (interpolation)
+    constexpr R g1 = INTERP ? R(10) : R(6), g2 = INTERP ? R(5) : R(3);
     R w0, w1, w2;
     if constexpr (sizeof(R) == 4) {
         w0 = rcp_w(e0 * e0);
-        w1 = R(6) * rcp_w(e1 * e1);
-        w2 = R(3) * rcp_w(e2 * e2);
+        w1 = g1 * rcp_w(e1 * e1);
+        w2 = g2 * rcp_w(e2 * e2);
     } else {
         const R s0 = e0 * e0, s1 = e1 * e1, s2 = e2 * e2;
         w0 = s1 * s2;
-        w1 = R(6) * (s0 * s2);
-        w2 = R(3) * (s0 * s1);
+        w1 = g1 * (s0 * s2);
+        w2 = g2 * (s0 * s1);
     }
     return (w0 * r0 + w1 * r1 + w2 * r2) * rcp_w(w0 + w1 + w2);
 }
@@ -879,12 +897,14 @@ inline float lane_next(float v) { return v; }
 
 // WENO interface flux between e and e+1 (local Lax-Friedrichs splitting), kept as
 // twice the flux: with v+ = C + al Q on e-2..e+2 and v- = C - al Q on e+3..e-1,
-//   2 F = v+_e + v-_{e+1} + (corr(v+) + corr(v-)) / 6
+//   2 F = v+_e + v-_{e+1} + (corr(v+) + corr(v-)) / 6      (reconstruction)
+//   2 F = v+_e + v-_{e+1} + (corr(v+) + corr(v-)) / 8      (interpolation form)
 // (the split fluxes are (C +- al Q) / 2; their smoothness indicators scale by 4, so the
 // weights take 4 epsh)
 // LANES (build option above): the neighbours of an interior point from adjacent lanes.
-template <class C, bool LANES = false>
-AT_HD AT_FI void iface_flux(const QV<C>& L, const PhysP& P, int64_t e, bool interior = false) {
+// INTERP: the interpolation form (the corrections are 8 (vhat - v2) there).
+template <class C, bool LANES, bool INTERP>
+AT_HD AT_FI void iface_flux_form(const QV<C>& L, const PhysP& P, int64_t e, bool interior) {
     using LR = typename C::lreal;
     const LR a0 = L.lam[e], a1 = L.lam[e + 1];
     const LR al = a0 > a1 ? a0 : a1;
@@ -915,10 +935,17 @@ AT_HD AT_FI void iface_flux(const QV<C>& L, const PhysP& P, int64_t e, bool inte
             vp[m] = c[m] + al * q[m];
             vm[m] = c[5 - m] - al * q[5 - m];
         }
-        const LR cp = weno5_corr<LR>(eps, vp[0], vp[1], vp[2], vp[3], vp[4]);
-        const LR cm = weno5_corr<LR>(eps, vm[0], vm[1], vm[2], vm[3], vm[4]);
-        L.flux[f][e] = (vp[2] + vm[2]) + (cp + cm) * LR(1.0 / 6.0);
+        const LR cp = weno5_corr<LR, INTERP>(eps, vp[0], vp[1], vp[2], vp[3], vp[4]);
+        const LR cm = weno5_corr<LR, INTERP>(eps, vm[0], vm[1], vm[2], vm[3], vm[4]);
+        L.flux[f][e] = (vp[2] + vm[2]) + (cp + cm) * LR(INTERP ? 1.0 / 8.0 : 1.0 / 6.0);
     }
+}
+
+// the interface flux in the problem's form (a uniform branch: one problem per tile)
+template <class C, bool LANES = false>
+AT_HD AT_FI void iface_flux(const QV<C>& L, const PhysP& P, int64_t e, bool interior = false) {
+    if (P.interp) iface_flux_form<C, LANES, true>(L, P, e, interior);
+    else iface_flux_form<C, LANES, false>(L, P, e, interior);
 }
 
 // K at ext position e; q = the point's own state (qreal) for sources / primitives
@@ -1151,6 +1178,7 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const AT_CONST Pr
     const int64_t n = uni(n_in);
     PhysP PP;
     PP.pde = uni(P.pde);
+    PP.interp = uni(P.interp);
     PP.c = uni(P.c); PP.alpha = uni(P.alpha); PP.r = uni(P.r); PP.gamma = uni(P.gamma);
     PP.q = uni(P.q); PP.ea = uni(P.ea); PP.b = uni(P.b); PP.mu = uni(P.mu);
     PP.kappa = uni(P.kappa); PP.rhoD = uni(P.rhoD); PP.eps = uni(P.eps);

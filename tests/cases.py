@@ -63,6 +63,11 @@ def single_cases():
         ("sod", W.euler_sod_c4(n=512, p=8), 30),
         ("sod_ragged_as", W.euler_sod_c4(n=500, p=9, mode="as"), 30),
         ("detonation", W.detonation_c5(n=1024, p=8, precision="fp64"), 20),
+        # WENO interpolation form (Sec. 3, eqs. interpS, fullSten; AT halo of eq. stenF)
+        ("sod_interp", W.euler_sod_c4(n=512, p=8).replace(scheme="weno5i"), 30),
+        ("burgers_interp_as", W.burgers_sweep(128, p=8, n_ref=128, mode="as").replace(scheme="weno5i"), 20),
+        ("advection_interp_ragged", W.advection_e1(60, p=7).replace(scheme="weno5i"), 20),
+        ("detonation_interp", W.detonation_c5(n=1024, p=8, precision="fp64").replace(scheme="weno5i"), 20),
         ("flame", W.reactive_ns_c2(n=512, p=8), 20),
         ("flame_fd4_rk2", W.reactive_ns_c2(n=300, p=5, scheme="fd4").replace(rk="rk2"), 20),
         # non-periodic ends with non-reflecting conditions (acoustic pulse, Sec. 5.1)
