@@ -55,7 +55,7 @@ def kernel_hash() -> str:
 
 # default time levels of the AT halo extrapolation by scheme: 3 for the 4th- and 8th-order
 # central schemes (Table A), 2 for 2nd order and AT-WENO (linear in time)
-AT_LEVELS = {"fd2": 2, "fd4": 3, "fd8": 3, "weno5": 2}
+AT_LEVELS = {"fd2": 2, "fd4": 3, "fd8": 3, "weno5": 2, "weno5i": 2}
 
 
 def algorithmic_bytes_per_step(prs, solver) -> dict:
@@ -231,7 +231,7 @@ def _ref_job(args):
     return oracle.run(pr.replace(precision="fp64"), steps)
 
 
-def run_other(name, steps, warmup, accuracy=True, workers=16):
+def run_other(name, steps, warmup, accuracy=True, workers=16, scheme=None):
     """Timing of both forms of another configuration, in the batched launch form with
     HIP graphs, and (accuracy) the error of each form against the oracle per field after
     the configuration's stated length, in the same launch form."""
@@ -239,6 +239,12 @@ def run_other(name, steps, warmup, accuracy=True, workers=16):
     from paper_2204_01133_amd import binding
     desc, make = OTHER_CONFIGS[name]
     base = make()
+    if scheme is not None:
+        # the WENO configurations in the interpolation form (Sec. 3, eqs. interpS, fullSten)
+        if any(p.scheme not in ("weno5", "weno5i") for p in base) or scheme not in ("weno5", "weno5i"):
+            raise SystemExit(f"--scheme {scheme}: only the WENO configurations take another WENO form")
+        base = [p.replace(scheme=scheme) for p in base]
+        desc = desc.replace("AT-WENO5", "AT-WENO5 interpolation form" if scheme == "weno5i" else "AT-WENO5")
     pts = W.total_points(base)
     stages = {"rk4": 4, "ssprk3": 3, "rk2": 2, "fe": 1}[base[0].rk]
     acc_steps = ACC_STEPS.get(name, base[0].steps)
@@ -305,6 +311,8 @@ def main():
     ap.add_argument("--config", default="c3", choices=["c3"] + sorted(OTHER_CONFIGS),
                     help="c3 (default): the headline line; others: both forms, timing and accuracy")
     ap.add_argument("--no-accuracy", action="store_true", help="other configurations: timing only")
+    ap.add_argument("--scheme", default=None, choices=["weno5", "weno5i"],
+                    help="WENO configurations: reconstruction (weno5) or interpolation form (weno5i)")
     ap.add_argument("--warmup-s", type=float, default=WARMUP_S,
                     help="seconds of untimed stepping before each timed form (0 for profiler runs)")
     ap.add_argument("--cpu-steps", type=int, default=800,
@@ -327,7 +335,8 @@ def main():
     workers = max(1, min(16, info["affinity"] or 1))
 
     if args.config != "c3":
-        run_other(args.config, args.steps, args.warmup, accuracy=not args.no_accuracy, workers=workers)
+        run_other(args.config, args.steps, args.warmup, accuracy=not args.no_accuracy, workers=workers,
+                  scheme=args.scheme)
         return
 
     base = W.batched_adr_c3()

@@ -941,13 +941,6 @@ AT_HD AT_FI void iface_flux_form(const QV<C>& L, const PhysP& P, int64_t e, bool
     }
 }
 
-// the interface flux in the problem's form (a uniform branch: one problem per tile)
-template <class C, bool LANES = false>
-AT_HD AT_FI void iface_flux(const QV<C>& L, const PhysP& P, int64_t e, bool interior = false) {
-    if (P.interp) iface_flux_form<C, LANES, true>(L, P, e, interior);
-    else iface_flux_form<C, LANES, false>(L, P, e, interior);
-}
-
 // K at ext position e; q = the point's own state (qreal) for sources / primitives
 // FP32 scalar FD kind: -c u_x + alpha u_xx (+ r u (1 - u)) at ext position e whose own
 // hi and lo values hc, lc the caller holds (they equal the region's values at e), as
@@ -1928,32 +1921,39 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const AT_CONST Pr
         const QV<C>& Wc = (C::HILO && s == 0) ? L.win0 : L.win[s & 1];   // stage 0: u^n
         const QV<C>& Wn = L.win[(s + 1) & 1];
 
-        // B1 (WENO): interface fluxes
+        // B1 (WENO): interface fluxes, the phase compiled once per form (reconstruction or
+        // interpolation) and chosen by a uniform branch around it
         if constexpr (C::WENO) {
-            rt.each([&](int tid, TS<C>& ts) {
-                if (own_active) {
+            auto fluxes = [&](auto form) {
+                constexpr bool INTERP = decltype(form)::value;
+                rt.each([&](int tid, TS<C>& ts) {
+                    if (own_active) {
 #pragma unroll
-                    for (int k = 0; k < PPT; ++k) {
-                        const int e = ts.e[k];
-                        if (k > 0) sched_fence();
-                        // right interface of the point
-                        if (e >= 0) iface_flux<C, WENO_DPP && C::F32>(Mc, PP, e, ts.eb[k] != 0);
+                        for (int k = 0; k < PPT; ++k) {
+                            const int e = ts.e[k];
+                            if (k > 0) sched_fence();
+                            // right interface of the point
+                            if (e >= 0)
+                                iface_flux_form<C, WENO_DPP && C::F32, INTERP>(Mc, PP, e, ts.eb[k] != 0);
+                        }
+                        // left interface of each PE's first point (its left neighbour is a
+                        // halo slot), as a short work list of its own
+                        sched_fence();
+                        for (int b = first_item(tid, nth, 2 * s + 2); b < t.npe; b += nth)
+                            iface_flux_form<C, false, INTERP>(Mc, PP, L.pelo[b] + 2 * H * b + H - 1, false);
                     }
-                    // left interface of each PE's first point (its left neighbour is a halo
-                    // slot), as a short work list of its own
-                    sched_fence();
-                    for (int b = first_item(tid, nth, 2 * s + 2); b < t.npe; b += nth)
-                        iface_flux<C>(Mc, PP, L.pelo[b] + 2 * H * b + H - 1);
-                }
-                if (win_active) {
-                    const int rlo = (s + 1) * H, rhi = WL - (s + 1) * H;
-                    const int ni = rhi - rlo + 1;                 // interfaces rlo-1 .. rhi-1
-                    for (int idx = first_item(tid, nth, 2 * s + 1); idx < (t.npe + 1) * ni; idx += nth) {
-                        const int b = idx / ni, j = rlo - 1 + (idx - b * ni);
-                        iface_flux<C>(Wc, PP, b * WL + j);
+                    if (win_active) {
+                        const int rlo = (s + 1) * H, rhi = WL - (s + 1) * H;
+                        const int ni = rhi - rlo + 1;                 // interfaces rlo-1 .. rhi-1
+                        for (int idx = first_item(tid, nth, 2 * s + 1); idx < (t.npe + 1) * ni; idx += nth) {
+                            const int b = idx / ni, j = rlo - 1 + (idx - b * ni);
+                            iface_flux_form<C, false, INTERP>(Wc, PP, b * WL + j, false);
+                        }
                     }
-                }
-            });
+                });
+            };
+            if (PP.interp) fluxes(std::true_type{});
+            else fluxes(std::false_type{});
             rt.sync();
         }
 
