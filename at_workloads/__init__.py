@@ -39,6 +39,8 @@ RKS = ("fe", "rk2", "ssprk3", "rk4")
 GRANULARITIES = ("per_pe", "per_pe_side", "per_boundary")
 PRECISIONS = ("fp64", "fp32c", "fp32")
 BCS = ("periodic", "nscbc")
+# reactive NS: AT on the convective fluxes ("flux") or, by the chain rule, on the primitives ("chain")
+FORMS = ("flux", "chain")
 
 # Probability sets of Table dels (Sec. 5): [p0 p1 p2].
 DELAY_SETS = {
@@ -85,6 +87,7 @@ class Problem:
     granularity: str = "per_pe"
     at_levels: int = 0                # J time levels of the AT extrapolation (0: scheme default)
     bc: str = "periodic"              # "periodic", or "nscbc": two ends with non-reflecting conditions
+    form: str = "flux"                # reactive NS: "flux" or "chain" (chain rule on the primitives)
     x0: float = 0.0
     lx: float = 1.0
     c: float = 0.0
@@ -107,7 +110,7 @@ class Problem:
     def __post_init__(self):
         assert self.pde in PDES and self.scheme in SCHEMES and self.mode in MODES
         assert self.rk in RKS and self.granularity in GRANULARITIES
-        assert self.precision in PRECISIONS and self.bc in BCS
+        assert self.precision in PRECISIONS and self.bc in BCS and self.form in FORMS
         self.q0 = np.ascontiguousarray(self.q0, dtype=np.float64).reshape(nfields(self.pde), self.n)
         if self.cdf:
             assert len(self.cdf) == self.kmax, "cdf needs kmax thresholds"

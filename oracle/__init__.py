@@ -27,6 +27,7 @@ PDE_IDS = {"adv_diff": 0, "adr_logistic": 1, "burgers": 2, "euler": 3, "reactive
            "reactive_ns": 5}
 SCHEME_IDS = {"fd2": 0, "fd4": 1, "fd8": 2, "weno5": 3, "weno5i": 4}
 MODE_IDS = {"sync": 0, "as": 1, "at": 2}
+FORM_IDS = {"flux": 0, "chain": 1}
 RK_IDS = {"fe": 0, "rk2": 1, "ssprk3": 2, "rk4": 3}
 GRAN_IDS = {"per_pe": 0, "per_pe_side": 1, "per_boundary": 2}
 BC_IDS = {"periodic": 0, "nscbc": 1}
@@ -47,6 +48,7 @@ class OrcProblem(ctypes.Structure):
         ("rk", ctypes.c_int32), ("granularity", ctypes.c_int32), ("kmax", ctypes.c_int32),
         ("n", ctypes.c_int64), ("p", ctypes.c_int32), ("n_cdf", ctypes.c_int32),
         ("at_levels", ctypes.c_int32), ("bc", ctypes.c_int32),
+        ("form", ctypes.c_int32), ("pad_form", ctypes.c_int32),
         ("cdf", ctypes.c_uint64 * 16),
         ("x0", ctypes.c_double), ("lx", ctypes.c_double), ("dt", ctypes.c_double),
         ("c", ctypes.c_double), ("alpha", ctypes.c_double), ("r", ctypes.c_double),
@@ -131,6 +133,7 @@ def to_struct(pr) -> OrcProblem:
     s.n_cdf = len(pr.cdf)
     s.at_levels = int(pr.at_levels)
     s.bc = BC_IDS[getattr(pr, "bc", "periodic")]
+    s.form = FORM_IDS[getattr(pr, "form", "flux")]
     for i, v in enumerate(pr.cdf):
         s.cdf[i] = int(v)
     for name in ("x0", "lx", "dt", "c", "alpha", "r", "gamma", "q", "ea", "b", "mu", "pr", "le",

@@ -152,7 +152,8 @@ static int is_weno(const orc_problem* pb) { return pb->scheme == ORC_WENO5 || pb
 static int nquant(const orc_problem* pb) {
     int F = orc_nfields(pb->pde);
     if (is_weno(pb)) return 2 * F;                 /* Q_f then C_f             */
-    if (pb->pde == ORC_PDE_REACTIVE_NS) return 7;  /* C1..C4, u, T, Y          */
+    if (pb->pde == ORC_PDE_REACTIVE_NS)            /* C1..C4, u, T, Y (flux)   */
+        return pb->form == 1 ? 5 : 7;              /* rho, u, p, T, Y (chain)  */
     return 1;                                      /* u                        */
 }
 
@@ -197,8 +198,12 @@ static void quantities(const orc_problem* pb, const double* q, double* g) {
     }
     if (pb->pde == ORC_PDE_REACTIVE_NS) {
         double C[MAXF], rho, u, T, Y;
-        conv_flux(pb, q, C);
         reactive_primitives(pb, q, &rho, &u, &T, &Y);
+        if (pb->form == 1) {
+            g[0] = rho; g[1] = u; g[2] = rho * T; g[3] = T; g[4] = Y;
+            return;
+        }
+        conv_flux(pb, q, C);
         g[0] = C[0]; g[1] = C[1]; g[2] = C[2]; g[3] = C[3]; g[4] = u; g[5] = T; g[6] = Y;
         return;
     }
@@ -486,10 +491,33 @@ static void rhs_region(const orc_problem* pb, int64_t lo, int64_t np, double** g
             }
             double rho, u, T, Y;
             reactive_primitives(pb, q, &rho, &u, &T, &Y);
-            double dC0 = d1(g[0], e, H, c1, dx), dC1 = d1(g[1], e, H, c1, dx);
-            double dC2 = d1(g[2], e, H, c1, dx), dC3 = d1(g[3], e, H, c1, dx);
-            double ux = d1(g[4], e, H, c1, dx), uxx = d2(g[4], e, H, c2, dx);
-            double Txx = d2(g[5], e, H, c2, dx), Yxx = d2(g[6], e, H, c2, dx);
+            double dC0, dC1, dC2, dC3, ux, uxx, Txx, Yxx;
+            if (pb->form == 1) {
+                /* chain rule: the convective products differentiated through the
+                 * primitives, e.g. (rho u Y)_x = rho u Y_x + rho u_x Y + rho_x u Y */
+                const double p = rho * T;
+                double rx = d1(g[0], e, H, c1, dx), px = d1(g[2], e, H, c1, dx);
+                double Yx = d1(g[4], e, H, c1, dx);
+                ux = d1(g[1], e, H, c1, dx);
+                uxx = d2(g[1], e, H, c2, dx);
+                Txx = d2(g[3], e, H, c2, dx);
+                Yxx = d2(g[4], e, H, c2, dx);
+                /* rho E = p/(gamma-1) + rho u^2/2 + q rho Y */
+                double dE = px / (gm - 1.0) + 0.5 * rx * u * u + rho * u * ux + pb->q * (rx * Y + rho * Yx);
+                dC0 = rx * u + rho * ux;
+                dC1 = rx * u * u + 2.0 * rho * u * ux + px;
+                dC2 = ux * (q[2] + p) + u * (dE + px);
+                dC3 = rho * u * Yx + rho * ux * Y + rx * u * Y;
+            } else {
+                dC0 = d1(g[0], e, H, c1, dx);
+                dC1 = d1(g[1], e, H, c1, dx);
+                dC2 = d1(g[2], e, H, c1, dx);
+                dC3 = d1(g[3], e, H, c1, dx);
+                ux = d1(g[4], e, H, c1, dx);
+                uxx = d2(g[4], e, H, c2, dx);
+                Txx = d2(g[5], e, H, c2, dx);
+                Yxx = d2(g[6], e, H, c2, dx);
+            }
             K[0][j] = -dC0;
             K[1][j] = -dC1 + (4.0 / 3.0) * pb->mu * uxx;
             K[2][j] = -dC2 + (4.0 / 3.0) * pb->mu * (ux * ux + u * uxx) + kappa * Txx
@@ -537,6 +565,9 @@ static int validate(const orc_problem* pb) {
         break;
     }
     if (pb->bc != 0 && pb->bc != 1) return ORC_EINVAL;
+    /* the chain-rule form: reactive NS with periodic ends */
+    if (pb->form != 0 && pb->form != 1) return ORC_EINVAL;
+    if (pb->form == 1 && (pb->pde != ORC_PDE_REACTIVE_NS || pb->bc != 0)) return ORC_EINVAL;
     if (pb->bc == 1) {
         /* the end closure reads four points inside the first and the last PE */
         if (pb->pde != ORC_PDE_REACTIVE_NS) return ORC_EINVAL;

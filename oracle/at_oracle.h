@@ -30,6 +30,10 @@
  *     extrapolated values).
  *   - AS mode: standard schemes used with the delayed level (J = 1, eq.
  *     async-fde, eq. asweno).  SYNC mode: the plain periodic scheme.
+ *   - reactive NS in chain-rule form (form = 1, Sec. 4 after eq. convEq, and the
+ *     memory-compute remark of Sec. 6): the derivatives of the convective products
+ *     expanded by the chain rule into derivatives of the primitives rho, u, p, Y, so
+ *     that the AT halo carries primitives (rho, u, p, T, Y) instead of fluxes.
  *   - non-periodic ends (bc = 1, the acoustic-wave case of Sec. 5.1 and the
  *     boundary remarks of Sec. 6): second-order central differences at the
  *     points closer to an end than the interior stencil reaches, second-order
@@ -67,6 +71,10 @@ typedef struct orc_problem {
     int32_t at_levels;    /* J, time levels of the AT extrapolation; 0: default  */
     int32_t bc;           /* 0: periodic; 1: two physical ends with non-reflecting
                              characteristic conditions (reactive NS, central FD)  */
+    int32_t form;         /* reactive NS: 0 = the convective fluxes differentiated
+                             (AT on C1..C4); 1 = chain rule on the primitives (AT on
+                             rho, u, p, T, Y), Sec. 4 after eq. convEq             */
+    int32_t pad_form;
     uint64_t cdf[16];     /* cumulative thresholds on a 2^32 scale               */
     double x0, lx, dt;
     double c, alpha, r, gamma, q, ea, b, mu, pr, le, weno_eps;

@@ -57,6 +57,7 @@ def _zero_override(pr, steps):
     lambda: W.euler_sod_c4(n=256, p=8, steps=20).replace(scheme="weno5i"),
     lambda: W.burgers_sweep(64, p=8),
     lambda: W.reactive_ns_c2(n=256, p=8, steps=10),
+    lambda: W.reactive_ns_c2(n=256, p=8, steps=10).replace(form="chain"),
     lambda: W.detonation_c5(n=512, p=8, steps=10, precision="fp64"),
 ])
 @pytest.mark.parametrize("mode", ["at", "as"])
