@@ -231,7 +231,7 @@ def _ref_job(args):
     return oracle.run(pr.replace(precision="fp64"), steps)
 
 
-def run_other(name, steps, warmup, accuracy=True, workers=16, scheme=None):
+def run_other(name, steps, warmup, accuracy=True, workers=16, scheme=None, form=None):
     """Timing of both forms of another configuration, in the batched launch form with
     HIP graphs, and (accuracy) the error of each form against the oracle per field after
     the configuration's stated length, in the same launch form."""
@@ -245,6 +245,12 @@ def run_other(name, steps, warmup, accuracy=True, workers=16, scheme=None):
             raise SystemExit(f"--scheme {scheme}: only the WENO configurations take another WENO form")
         base = [p.replace(scheme=scheme) for p in base]
         desc = desc.replace("AT-WENO5", "AT-WENO5 interpolation form" if scheme == "weno5i" else "AT-WENO5")
+    if form is not None:
+        # reactive NS: AT on the fluxes or, by the chain rule, on the primitives (Sec. 4)
+        if any(p.pde != "reactive_ns" for p in base):
+            raise SystemExit(f"--form {form}: only the reactive NS configuration has the chain-rule form")
+        base = [p.replace(form=form) for p in base]
+        desc += ", chain rule on the primitives" if form == "chain" else ", fluxes differentiated"
     pts = W.total_points(base)
     stages = {"rk4": 4, "ssprk3": 3, "rk2": 2, "fe": 1}[base[0].rk]
     acc_steps = ACC_STEPS.get(name, base[0].steps)
@@ -311,6 +317,8 @@ def main():
     ap.add_argument("--config", default="c3", choices=["c3"] + sorted(OTHER_CONFIGS),
                     help="c3 (default): the headline line; others: both forms, timing and accuracy")
     ap.add_argument("--no-accuracy", action="store_true", help="other configurations: timing only")
+    ap.add_argument("--form", default=None, choices=["flux", "chain"],
+                    help="reactive NS configuration: AT on the fluxes or on the primitives (chain rule)")
     ap.add_argument("--scheme", default=None, choices=["weno5", "weno5i"],
                     help="WENO configurations: reconstruction (weno5) or interpolation form (weno5i)")
     ap.add_argument("--warmup-s", type=float, default=WARMUP_S,
@@ -336,7 +344,7 @@ def main():
 
     if args.config != "c3":
         run_other(args.config, args.steps, args.warmup, accuracy=not args.no_accuracy, workers=workers,
-                  scheme=args.scheme)
+                  scheme=args.scheme, form=args.form)
         return
 
     base = W.batched_adr_c3()

@@ -77,6 +77,10 @@ enum at_precision { AT_FP64 = 0, AT_FP32C = 1, AT_FP32 = 2 };
  *                2 for FD2 and the WENO schemes; 2 levels make the AT-WENO
  *                interpolation form the five-point stencil of eq. stenF).
  *   n, p         points and PEs, 1 <= p <= n; PE k owns [floor(kn/p), floor((k+1)n/p)).
+ *   form         reactive NS: 0 = the convective fluxes are differentiated (the AT
+ *                halo carries C1..C4, u, T, Y); 1 = the chain rule expands their
+ *                derivatives into those of the primitives (Sec. 4 after eq. convEq:
+ *                the AT halo carries rho, u, p, T, Y); periodic problems only.
  *   x0, lx, dt   grid x_j = x0 + (j + 1/2) lx/n; constant time step.
  *   c, alpha, r  advection speed, diffusivity, logistic rate.
  *   gamma, q, ea, b, mu, pr, le  gas constant ratio (R = 1), heat release,
@@ -99,7 +103,7 @@ typedef struct at_problem_desc {
     int32_t pde, scheme, mode, rk, granularity, precision;
     int32_t kmax, at_levels, n_cdf, bc;
     int64_t n;
-    int32_t p, pad1;
+    int32_t p, form;
     uint64_t cdf[16];
     double x0, lx, dt;
     double c, alpha, r, gamma, q, ea, b, mu, pr, le, weno_eps;

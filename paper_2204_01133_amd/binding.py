@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(os.environ.get("AT_BUILD_DIR") or os.path.join(_HERE, "_
 
 PDE_IDS = {"adv_diff": 0, "adr_logistic": 1, "burgers": 2, "euler": 3, "reactive_euler": 4,
            "reactive_ns": 5}
+FORM_IDS = {"flux": 0, "chain": 1}
 SCHEME_IDS = {"fd2": 0, "fd4": 1, "fd8": 2, "weno5": 3, "weno5i": 4}
 MODE_IDS = {"sync": 0, "as": 1, "at": 2}
 RK_IDS = {"fe": 0, "rk2": 1, "ssprk3": 2, "rk4": 3}
@@ -36,7 +37,7 @@ class AtProblemDesc(ctypes.Structure):
         ("rk", ctypes.c_int32), ("granularity", ctypes.c_int32), ("precision", ctypes.c_int32),
         ("kmax", ctypes.c_int32), ("at_levels", ctypes.c_int32), ("n_cdf", ctypes.c_int32),
         ("bc", ctypes.c_int32),
-        ("n", ctypes.c_int64), ("p", ctypes.c_int32), ("pad1", ctypes.c_int32),
+        ("n", ctypes.c_int64), ("p", ctypes.c_int32), ("form", ctypes.c_int32),
         ("cdf", ctypes.c_uint64 * 16),
         ("x0", ctypes.c_double), ("lx", ctypes.c_double), ("dt", ctypes.c_double),
         ("c", ctypes.c_double), ("alpha", ctypes.c_double), ("r", ctypes.c_double),
@@ -77,6 +78,7 @@ def describe(pr) -> AtProblemDesc:
     d.at_levels = pr.at_levels
     d.n_cdf = len(pr.cdf)
     d.bc = BC_IDS[getattr(pr, "bc", "periodic")]
+    d.form = FORM_IDS[getattr(pr, "form", "flux")]
     for i, v in enumerate(pr.cdf):
         d.cdf[i] = int(v)
     d.n = pr.n

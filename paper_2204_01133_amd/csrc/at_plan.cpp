@@ -127,6 +127,9 @@ static int validate(const at_problem_desc& d, int idx, std::string& err) {
     if (d.at_levels < 0 || d.at_levels > 6) return bad("at_levels must be in 0..6");
     if (!(d.dt > 0.0) || !(d.lx > 0.0)) return bad("dt and lx must be positive");
     if (d.bc != 0 && d.bc != 1) return bad("unknown bc");
+    if (d.form != 0 && d.form != 1) return bad("unknown form");
+    if (d.form == 1 && (d.pde != AT_PDE_REACTIVE_NS || d.bc != 0))
+        return bad("the chain-rule form is defined for periodic reactive NS problems");
     return AT_OK;
 }
 
@@ -414,6 +417,7 @@ void fill_probdev(const Plan& plan, int b, unsigned char* base, ProbDev& P, int6
     P.keep_lo = d.precision == AT_FP32C;
     P.bc = d.bc;
     P.interp = d.scheme == AT_WENO5I ? 1 : 0;
+    P.form = d.form;
     P.S = pi.S;
     P.F = pi.F;
     for (int i = 0; i < 16; ++i) P.cdf[i] = d.cdf[i];

@@ -157,6 +157,7 @@ struct ProbDev {
     int32_t p, pde, mode, gran, kmax, J, D, n_cdf, keep_lo, S, F;
     int32_t bc;              // 1: non-periodic ends with non-reflecting conditions
     int32_t interp;          // WENO kinds: 1 = interpolation form (AT_WENO5I)
+    int32_t form, pad_form;  // reactive NS: 1 = chain rule on the primitives
     uint64_t cdf[16];
     uint64_t seed;
     int64_t pid;
@@ -198,6 +199,7 @@ enum KFlags { KF_STAGE_IO = 1, KF_LOG = 2, KF_XCD = 4, KF_HALO_LDS = 8 };
 struct PhysP {
     int pde;
     int interp;           // WENO kinds: interpolation form of the interface values
+    int form;             // reactive NS: chain rule on the primitives
     double c, alpha, r, gamma, q, ea, b, mu, kappa, rhoD, eps, inv_dx, inv_dx2, dt;
     float cf, alphaf, rf, inv_dxf, inv_dx2f;     // FP32 copies for the FP32 forms
     double lp[4], lm[4];                           // scalar FD kind: combined stencil
@@ -253,6 +255,7 @@ AT_HD AT_FI ProbDev uniform_copy(const AT_CONST ProbDev& P) {
     u.keep_lo = uni(P.keep_lo); u.S = uni(P.S); u.F = uni(P.F);
     u.bc = uni(P.bc);
     u.interp = uni(P.interp);
+    u.form = uni(P.form);
     u.seed = (uint64_t)uni((int64_t)P.seed);
     u.pid = uni(P.pid);
     u.dt = uni(P.dt); u.inv_dx = uni(P.inv_dx); u.inv_dx2 = uni(P.inv_dx2);
@@ -813,13 +816,18 @@ AT_HD AT_FI void put_quant(const QV<C>& L, const PhysP& P, int64_t e, const type
         double rho, u, T, Y;
         reactive_prims(P, qd, rho, u, T, Y);
         const double p = rho * T;
-        L.g[0][e] = (LR)qd[1];
-        L.g[1][e] = (LR)(qd[1] * u + p);
-        L.g[2][e] = (LR)(u * (qd[2] + p));
-        L.g[3][e] = (LR)(qd[3] * u);
-        L.g[4][e] = (LR)u;
-        L.g[5][e] = (LR)T;
-        L.g[6][e] = (LR)Y;
+        // flux form: C1..C4, u, T, Y; chain rule: the primitives rho, u, p, T, Y (slots
+        // 5, 6 unused), chosen value by value (one store per slot)
+        const bool ch = P.form != 0;
+        L.g[0][e] = (LR)(ch ? rho : qd[1]);
+        L.g[1][e] = (LR)(ch ? u : qd[1] * u + p);
+        L.g[2][e] = (LR)(ch ? p : u * (qd[2] + p));
+        L.g[3][e] = (LR)(ch ? T : qd[3] * u);
+        L.g[4][e] = (LR)(ch ? Y : u);
+        if (!ch) {
+            L.g[5][e] = (LR)T;
+            L.g[6][e] = (LR)Y;
+        }
     }
 }
 
@@ -848,8 +856,14 @@ AT_HD AT_FI void quant_values(const PhysP& P, const typename C::qreal* q, typena
         double rho, u, T, Y;
         reactive_prims(P, qd, rho, u, T, Y);
         const double p = rho * T;
-        g[0] = qd[1]; g[1] = qd[1] * u + p; g[2] = u * (qd[2] + p); g[3] = qd[3] * u;
-        g[4] = u; g[5] = T; g[6] = Y;
+        const bool ch = P.form != 0;   // chain rule: the primitives (slots 5, 6 unused)
+        g[0] = ch ? rho : qd[1];
+        g[1] = ch ? u : qd[1] * u + p;
+        g[2] = ch ? p : u * (qd[2] + p);
+        g[3] = ch ? T : qd[3] * u;
+        g[4] = ch ? Y : u;
+        g[5] = ch ? 0.0 : T;
+        g[6] = ch ? 0.0 : Y;
         lam = Q(0);
     }
 }
@@ -1023,6 +1037,25 @@ AT_HD AT_FI void rhs_at(const QV<C>& L, const PhysP& P, int64_t e, const typenam
         double qd[4] = {(double)q[0], (double)q[1], (double)q[2], (double)q[3]};
         double rho, u, T, Y;
         reactive_prims(P, qd, rho, u, T, Y);
+        if (P.form) {
+            // chain rule (Sec. 4 after eq. convEq): the convective products differentiated
+            // through the primitives rho, u, p, Y, e.g. (rho u Y)_x = rho u Y_x + rho u_x Y
+            // + rho_x u Y; rho E = p/(gamma-1) + rho u^2/2 + q rho Y
+            const LR rx = d1<C>(L.g[0], e) * idx, ux = d1<C>(L.g[1], e) * idx;
+            const LR px = d1<C>(L.g[2], e) * idx, Yx = d1<C>(L.g[4], e) * idx;
+            const LR uxx = d2<C>(L.g[1], e) * idx2, Txx = d2<C>(L.g[3], e) * idx2;
+            const LR Yxx = d2<C>(L.g[4], e) * idx2;
+            const LR r = LR(rho), uu = LR(u), YY = LR(Y), pp = LR(rho * T), rE = LR(qd[2]);
+            const LR mu43 = LR(4.0 / 3.0) * LR(P.mu);
+            const LR dE = px * LR(1.0 / (P.gamma - 1.0)) + LR(0.5) * rx * uu * uu + r * uu * ux +
+                          LR(P.q) * (rx * YY + r * Yx);
+            K[0] = -(rx * uu + r * ux);
+            K[1] = -(rx * uu * uu + LR(2) * r * uu * ux + px) + mu43 * uxx;
+            K[2] = -(ux * (rE + pp) + uu * (dE + px)) + mu43 * (ux * ux + uu * uxx) + LR(P.kappa) * Txx +
+                   LR(P.q * P.rhoD) * Yxx;
+            K[3] = -(r * uu * Yx + r * ux * YY + rx * uu * YY) + LR(P.rhoD) * Yxx + LR(arrhenius(P, qd));
+            return;
+        }
         const LR ux = d1<C>(L.g[4], e) * idx, uxx = d2<C>(L.g[4], e) * idx2;
         const LR Txx = d2<C>(L.g[5], e) * idx2, Yxx = d2<C>(L.g[6], e) * idx2;
         const LR mu43 = LR(4.0 / 3.0) * LR(P.mu);
@@ -1172,6 +1205,7 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const AT_CONST Pr
     PhysP PP;
     PP.pde = uni(P.pde);
     PP.interp = uni(P.interp);
+    PP.form = uni(P.form);
     PP.c = uni(P.c); PP.alpha = uni(P.alpha); PP.r = uni(P.r); PP.gamma = uni(P.gamma);
     PP.q = uni(P.q); PP.ea = uni(P.ea); PP.b = uni(P.b); PP.mu = uni(P.mu);
     PP.kappa = uni(P.kappa); PP.rhoD = uni(P.rhoD); PP.eps = uni(P.eps);

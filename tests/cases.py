@@ -70,6 +70,9 @@ def single_cases():
         ("detonation_interp", W.detonation_c5(n=1024, p=8, precision="fp64").replace(scheme="weno5i"), 20),
         ("flame", W.reactive_ns_c2(n=512, p=8), 20),
         ("flame_fd4_rk2", W.reactive_ns_c2(n=300, p=5, scheme="fd4").replace(rk="rk2"), 20),
+        # chain-rule form of reactive NS (Sec. 4 after eq. convEq): AT on the primitives
+        ("flame_chain", W.reactive_ns_c2(n=512, p=8).replace(form="chain"), 20),
+        ("flame_chain_fd4_as_ragged", W.reactive_ns_c2(n=300, p=7, scheme="fd4", mode="as").replace(form="chain"), 20),
         # non-periodic ends with non-reflecting conditions (acoustic pulse, Sec. 5.1)
         ("acoustic_at", W.acoustic_wave(n=256, p=8, kmax=2), 60),
         ("acoustic_as_ragged", W.acoustic_wave(n=250, p=7, kmax=2, mode="as", x_peak=0.8), 40),
