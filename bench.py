@@ -123,6 +123,18 @@ def time_form(prs, steps, warmup, method="batch_step", graph_steps=GRAPH_STEPS, 
     return s, ms / 1000.0, wall, g
 
 
+def states_after(prs, steps, graph_steps, idx):
+    """States of problems idx after exactly `steps` batched steps of a fresh solver in the
+    timed launch form (the timed solvers run extra untimed warm-up steps, so their step
+    count is not the oracle's)."""
+    from paper_2204_01133_amd import ATSolver
+    s = ATSolver(prs, graph_steps=graph_steps)
+    s.batch_step(steps)
+    out = [s.state(i) for i in idx]
+    s.close()
+    return out
+
+
 def _oracle_job(args):
     """One sampled problem on the oracle: its state after `keep` steps (for the errors of
     the GPU forms) and the CPU seconds of all `steps` steps (creation not included)."""
@@ -370,11 +382,11 @@ def main():
 
     # FP64 batched, FP64 plain (one launch per problem, fewer steps: launch bound)
     prs64 = [p.replace(precision="fp64") for p in base]
-    s64, t64, _, _ = time_form(prs64, K, Wm)
+    s64, t64, _, g64 = time_form(prs64, K, Wm)
     bytes64 = algorithmic_bytes_per_step(prs64, s64)
     # FP32 batched with a 4-byte state (the low part is not kept across steps)
     prsf = [p.replace(precision="fp32") for p in base]
-    sf, tf, _, _ = time_form(prsf, K, Wm)
+    sf, tf, _, gf = time_form(prsf, K, Wm)
     bytesf = algorithmic_bytes_per_step(prsf, sf)
     kp = max(2, min(20, K // 50))
     _, tplain, _, _ = time_form(prs64, kp, 2, method="step", graph_steps=0)
@@ -391,9 +403,9 @@ def main():
         cpu_rate, owall, ocpu = None, 0.0, 0.0
     else:
         refs, owall, ocpu = oracle_sample(base, idx, total_steps, cpu_steps, workers)
-        err32 = max(norm_err(s32.state(i), r) for i, r in zip(idx, refs))
-        err64 = max(norm_err(s64.state(i), r) for i, r in zip(idx, refs))
-        errf = max(norm_err(sf.state(i), r) for i, r in zip(idx, refs))
+        err32 = max(norm_err(a, r) for a, r in zip(states_after(prs32, total_steps, g32, idx), refs))
+        err64 = max(norm_err(a, r) for a, r in zip(states_after(prs64, total_steps, g64, idx), refs))
+        errf = max(norm_err(a, r) for a, r in zip(states_after(prsf, total_steps, gf, idx), refs))
         cpu_rate = sample_pts * S * cpu_steps / owall
 
     traffic = None

@@ -84,10 +84,14 @@ static void run_group(EmuCtx& c, const Group& g, int s_begin, int s_end, int fla
         std::memset(lds.data(), 0xff, lds.size());
         CpuRT<C> rt;
         const Tile& t = a.tiles[ti];
-        if (s_begin == 0 && s_end == C::S - 1 && !(flags & KF_STAGE_IO))
-            tile_step<C, true>(rt, a, t, a.probs[t.prob], c.step, lds.data());
+        const bool whole = s_begin == 0 && s_end == C::S - 1 && !(flags & KF_STAGE_IO);
+        const bool staged = C::KIND == K_ADR && (flags & KF_HALO_LDS);
+        if (whole)
+            staged ? tile_step<C, true, true>(rt, a, t, a.probs[t.prob], c.step, lds.data())
+                   : tile_step<C, true, false>(rt, a, t, a.probs[t.prob], c.step, lds.data());
         else
-            tile_step<C, false>(rt, a, t, a.probs[t.prob], c.step, lds.data());
+            staged ? tile_step<C, false, true>(rt, a, t, a.probs[t.prob], c.step, lds.data())
+                   : tile_step<C, false, false>(rt, a, t, a.probs[t.prob], c.step, lds.data());
     }
 }
 

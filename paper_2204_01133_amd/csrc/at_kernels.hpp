@@ -59,7 +59,7 @@ __device__ __forceinline__ const AT_CONST T& const_ref(const T* p) {
     return *(const AT_CONST T*)p;
 }
 
-template <class C, bool STEP>
+template <class C, bool STEP, bool STAGED = false>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(STEP ? C::WAVES_STEP : C::WAVES_PER_EU)))
 void at_tile_kernel(KArgs a) {
     extern __shared__ __align__(16) unsigned char lds[];
@@ -69,12 +69,12 @@ void at_tile_kernel(KArgs a) {
     for (int it = blockIdx.x; it < a.ntiles; it += gridDim.x) {
         const int ti = remap ? xcd_item(it, a.ntiles) : it;
         const Tile t = const_ref(a.tiles + ti);
-        tile_step<C, STEP>(rt, a, t, const_ref(a.tprobs + ti), n, lds);
+        tile_step<C, STEP, STAGED>(rt, a, t, const_ref(a.tprobs + ti), n, lds);
         if (it + (int)gridDim.x < a.ntiles) rt.sync();   // LDS reused by the next tile
     }
 }
 
-template <class C, bool STEP>
+template <class C, bool STEP, bool STAGED>
 hipError_t launch_form(const KArgs& a, int grid, hipStream_t s) {
     // the dynamic-LDS limit is a property of the kernel on each device: raised once per
     // device (the current one, which the stream belongs to); safe under concurrent launches
@@ -84,21 +84,25 @@ hipError_t launch_form(const KArgs& a, int grid, hipStream_t s) {
     if (e != hipSuccess) return e;
     const uint64_t bit = dev < 64 ? uint64_t(1) << dev : 0;
     if (!(attr_done.load(std::memory_order_acquire) & bit)) {
-        e = hipFuncSetAttribute((const void*)at_tile_kernel<C, STEP>,
+        e = hipFuncSetAttribute((const void*)at_tile_kernel<C, STEP, STAGED>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         if (e != hipSuccess) return e;
         attr_done.fetch_or(bit, std::memory_order_acq_rel);
     }
-    hipLaunchKernelGGL((at_tile_kernel<C, STEP>), dim3(grid), dim3(BLOCK), (size_t)a.lds_bytes, s, a);
+    hipLaunchKernelGGL((at_tile_kernel<C, STEP, STAGED>), dim3(grid), dim3(BLOCK), (size_t)a.lds_bytes, s, a);
     return hipGetLastError();
 }
 
-// whole steps take the kernel whose stage range is fixed at compile time
+// whole steps take the kernel whose stage range is fixed at compile time; the scalar FD
+// kind with its strips staged in LDS (run option halo_lds) takes kernels of their own
 template <class C>
 hipError_t launch_variant(const KArgs& a, int grid, hipStream_t s) {
-    if (a.s_begin == 0 && a.s_end == C::S - 1 && !(a.flags & KF_STAGE_IO))
-        return launch_form<C, true>(a, grid, s);
-    return launch_form<C, false>(a, grid, s);
+    const bool whole = a.s_begin == 0 && a.s_end == C::S - 1 && !(a.flags & KF_STAGE_IO);
+    if constexpr (C::KIND == K_ADR) {
+        if (a.flags & KF_HALO_LDS)
+            return whole ? launch_form<C, true, true>(a, grid, s) : launch_form<C, false, true>(a, grid, s);
+    }
+    return whole ? launch_form<C, true, false>(a, grid, s) : launch_form<C, false, false>(a, grid, s);
 }
 
 // per-kind dispatchers (one translation unit each); return false if the key is not theirs

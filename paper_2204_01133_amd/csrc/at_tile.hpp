@@ -1186,7 +1186,9 @@ AT_HD AT_FI int64_t ring_lo_off(int s, int h, int f) { return (int64_t)C::H * C:
 
 // STEP: the launch is a whole step (stages 0..S-1, no stage inputs or outputs), so the
 // stage range is known at compile time; otherwise it is read from the arguments.
-template <class C, bool STEP, class RT>
+// STAGED (scalar FD kind, run option halo_lds): the delayed strips staged in LDS instead
+// of registers; a kernel of its own, so that the default kernel carries none of its code.
+template <class C, bool STEP, bool STAGED, class RT>
 AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const AT_CONST ProbDev& P_in, int64_t n_in,
                      unsigned char* lds_base) {
     const ProbDev P = uniform_copy(P_in);
@@ -1234,7 +1236,8 @@ AT_HD void tile_step(RT& rt, const KArgs& a, const Tile& t_in, const AT_CONST Pr
 
     // LDS layout sized by this tile (the launch allocates the largest over its tiles)
     // scalar FD kind: the delayed strips staged in LDS (run option) instead of registers
-    const bool staged = C::KIND == K_ADR && (a.flags & KF_HALO_LDS) != 0;
+    constexpr bool staged = STAGED && C::KIND == K_ADR;
+    AT_CHECK(staged == (C::KIND == K_ADR && (a.flags & KF_HALO_LDS) != 0), "halo staging", staged, a.flags);
     Layout<C> Lo;
     Lo.init(t.npts, t.npe, a.jmax, staged);
     AT_CHECK(Lo.total <= a.lds_bytes, "tile LDS", Lo.total, a.lds_bytes);
