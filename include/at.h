@@ -153,13 +153,16 @@ typedef struct at_run_opts {
 
 typedef struct at_ctx at_ctx;
 
-/* Validate the problems, plan tiles, ring and work list; no device memory is
+/* (Sec. 2.1, Fig. 1: the PE decomposition with buffer points; Sec. 2.2: the
+ * delayed time levels the AT halo needs.)  Validate the problems, plan the PE
+ * partitions, the tiles, the ring of delayed levels and the work list; no device memory is
  * touched.  *workspace_bytes receives the size of the device workspace.
  * Errors: AT_EINVAL (descriptor), AT_EUNSUPPORTED (e.g. a PE larger than a tile). */
 int at_init(const at_problem_desc* probs, int n_probs, const at_run_opts* opts, at_ctx** out,
             size_t* workspace_bytes);
 
-/* Hand over the caller-owned device workspace (>= workspace_bytes, 256-byte
+/* (Sec. 2.1-2.2: the states and the ring of past boundary levels live here.)
+ * Hand over the caller-owned device workspace (>= workspace_bytes, 256-byte
  * aligned) and the HIP stream (hipStream_t, NULL = default stream) on the
  * current device.  Uploads the problem tables (stream-ordered) and creates the
  * side streams and events of at_batch_step (one per kernel variant after the
@@ -185,26 +188,33 @@ int at_bind(at_ctx* ctx, void* d_workspace, size_t bytes, void* hip_stream);
 #define AT_SCRATCH_BYTES ((size_t)128 << 20)
 int at_bind_scratch(at_ctx* ctx, void* hip_stream);
 
-/* Set problem `prob`'s level-0 state: F x N doubles (structure of arrays,
+/* (Sec. 2.3, eq. rk1: u^0, the state the first step starts from.)
+ * Set problem `prob`'s level-0 state: F x N doubles (structure of arrays,
  * field-major) on the host (q_on_device = 0; copied before return) or on the
  * device (stream-ordered).  Resets the step counter of the context to 0 when
  * called before the first step; AT_ESTATE after stepping (use at_reset). */
 int at_set_state(at_ctx* ctx, int prob, const double* q, int q_on_device);
 
-/* Forget all progress: step counter and stage pointer to 0; states must be set again. */
+/* (Sec. 2.1: the delays are bounded by the levels held, so a new start holds none.)
+ * Forget all progress: step counter and stage pointer to 0; states must be set again. */
 int at_reset(at_ctx* ctx);
 
-/* One RK stage (1-based, 1..S) of the current step for every problem: draws
+/* (Sec. 2.3, eqs. rk1, rkat1: one stage, K_s from the AT halo of the delayed
+ * levels' synchronous stage values.)
+ * One RK stage (1-based, 1..S) of the current step for every problem: draws
  * the delays and builds the level's halo strips at stage 1, keeps stage
  * right-hand sides in the workspace, and at stage S forms u^{n+1} and
  * advances the step.  Stages must be called in order.  Needs stage_api.
  * Results equal at_step's.  Errors: AT_ESTATE, AT_EINVAL, AT_EHIP. */
 int at_rk_stage(at_ctx* ctx, int stage);
 
-/* Plain form: n_steps steps, each one fused all-stage kernel launch per problem. */
+/* (Sec. 2.3, eq. rk1: all S stages and the update, with the AT schemes of Sec. 2.2
+ * and Sec. 3 at PE boundaries.)
+ * Plain form: n_steps steps, each one fused all-stage kernel launch per problem. */
 int at_step(at_ctx* ctx, int n_steps);
 
-/* Batched form: n_steps steps, each one launch per kernel variant over the
+/* (Sec. 2.3, eq. rk1, as at_step.)
+ * Batched form: n_steps steps, each one launch per kernel variant over the
  * work list of all problems (persistent or one workgroup per tile), replayed
  * from captured HIP graphs of graph_steps steps when enabled.  The launches of
  * one step run concurrently: the first on the context's stream, the others on
@@ -213,26 +223,30 @@ int at_step(at_ctx* ctx, int n_steps);
  * context's stream.  Errors: AT_ESTATE, AT_EINVAL, AT_EHIP. */
 int at_batch_step(at_ctx* ctx, int n_steps);
 
-/* Copy problem `prob`'s current state out as F x N doubles (hi + lo for the
+/* (Sec. 2.3, eq. rk1: u^n.)
+ * Copy problem `prob`'s current state out as F x N doubles (hi + lo for the
  * FP32 forms).  out_on_device = 0: host buffer, synchronises the stream. */
 int at_get_state(at_ctx* ctx, int prob, double* out, int out_on_device);
 
-/* Delays drawn and used (effective, clamped to the held history) for steps
+/* (Sec. 2.1 and Table dels: the delay k~ of each PE and step.)
+ * Delays drawn and used (effective, clamped to the held history) for steps
  * [step0, step0 + n_steps), each P x 2 (PE, side) bytes; needs log_steps and
  * the steps to be inside the logged window.  Synchronises the stream. */
 int at_get_delays(at_ctx* ctx, int prob, int64_t step0, int n_steps, uint8_t* drawn,
                   uint8_t* effective);
 
-/* Replace the drawn delays of problem `prob` for steps [step0, step0+n_steps)
+/* (Sec. 2.1: the delays k~, here prescribed instead of drawn.)
+ * Replace the drawn delays of problem `prob` for steps [step0, step0+n_steps)
  * by sched (n_steps x P x 2 bytes, host).  Values above kmax: AT_ESTALE (the
  * ring holds only kmax + J levels).  n_steps = 0 clears.  Needs override_steps. */
 int at_set_delay_override(at_ctx* ctx, int prob, const uint8_t* sched, int64_t step0,
                           int n_steps);
 
-/* Wait for the context's stream. */
+/* (No passage: interface housekeeping.)  Wait for the context's stream. */
 int at_sync(at_ctx* ctx);
 
-/* Introspection: AT_Q_* keys below; value out.  Errors: AT_EINVAL. */
+/* (Sec. 2.1: sizes of the partition and its work.)
+ * Introspection: AT_Q_* keys below; value out.  Errors: AT_EINVAL. */
 enum at_query_key {
     AT_Q_STEP = 0,            /* current step n                                     */
     AT_Q_NUM_TILES = 1,       /* work items over all problems                        */
@@ -246,9 +260,14 @@ enum at_query_key {
 };
 int at_query(const at_ctx* ctx, int key, int64_t* value);
 
-/* Device stream the last launches went to (for event timing on that stream). */
+/* (No passage: interface housekeeping.)  Device stream the last launches went to
+ * (for event timing on that stream). */
 void* at_stream(const at_ctx* ctx);
 
+/* (No passage: interface housekeeping.)  Text of an error code; of the context's
+ * last error (its planner or HIP message); release of the context and of what
+ * at_bind created (streams, events, graphs; the caller's workspace stays the
+ * caller's). */
 const char* at_strerror(int code);
 const char* at_last_error(const at_ctx* ctx);
 void at_free(at_ctx* ctx);
