@@ -144,6 +144,47 @@ def test_tuned_cache_drives_the_solver(torch, tmp_path):
     assert solver(prs, tuned=cache, persistent=0).run_opts["persistent"] == 0
 
 
+def test_device_state_on_a_side_stream(torch):
+    """A solver on a stream that is not the caller's current one, fed and read through
+    device tensors (float32 input converted on the current stream, freed right after
+    the call; the output consumed on the current stream): the same state as the host
+    path, bit for bit."""
+    prs, _ = batch_case()
+    ref = _run(prs, 9, "batch_step")
+    st = torch.cuda.Stream()
+    s = solver(prs, stream=st, set_initial=False)
+    for b, pr in enumerate(prs):
+        q = torch.tensor(pr.q0, dtype=torch.float64, device="cuda")
+        s.set_state(b, q)
+        del q
+        torch.cuda.empty_cache()
+    with torch.cuda.stream(st):
+        s.batch_step(9)
+    got = []
+    for b in range(len(prs)):
+        t = s.state_device(b)
+        got.append((t * 1.0).cpu().numpy())      # consumed on the current stream
+    for a, b in zip(got, ref):
+        assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32c"])
+@pytest.mark.parametrize("make", [lambda: W.euler_sod_c4(n=2048, p=8), lambda: W.detonation_c5(n=2048, p=8, precision="fp64")],
+                         ids=["sod", "detonation"])
+def test_multi_pe_weno_tiles(torch, prec, make):
+    """WENO tiles of several PEs (forced by the tile size and budget) equal one PE per
+    tile bit for bit, and FP64 stays within 1e-12 of the oracle."""
+    pr = with_precision(make(), prec)
+    one = solver([pr], lds_budget=20 * 1024)                                  # one PE per tile
+    many = solver([pr], tile_points=1024, lds_budget=160 * 1024, tile_class=1)  # four per tile
+    assert one.query(1) == pr.p and many.query(1) == pr.p // 4
+    one.batch_step(15)
+    many.batch_step(15)
+    assert np.array_equal(one.state(0), many.state(0))
+    if prec == "fp64":
+        assert norm_err(pr, many.state(0), _oracle(pr, 15).state()) < 1e-12
+
+
 def test_graph_replay_on_torch_stream(torch):
     prs, _ = batch_case()
     st = torch.cuda.Stream()
