@@ -24,7 +24,9 @@ def full_length_cases():
     ns = np.array([p.n for p in prs])
     return {
         "c2": (W.reactive_ns_c2(), 2000),
+        "c2_chain": (W.reactive_ns_c2().replace(form="chain"), 2000),
         "c4": (W.euler_sod_c4(), 200),
+        "c4_interp": (W.euler_sod_c4().replace(scheme="weno5i"), 200),
         # the serial oracle takes seconds per step at 2^20 points
         "c5": (W.detonation_c5(), 20),
         "c5batch_min": (prs[int(ns.argmin())], 200),

@@ -330,31 +330,33 @@ def _field_report(name, prec, pr, got, ref):
     return errs
 
 
+@pytest.mark.parametrize("case", ["c4", "c4_interp"])
 @pytest.mark.parametrize("prec", ["fp64", "fp32c"])
-def test_full_c4(torch, full_refs, prec):
+def test_full_c4(torch, full_refs, prec, case):
     """The Euler shock tube at its full size and length (N 65,536, P 256, AT-WENO5 with
     delays up to 4, SSP-RK3, 200 steps) in the launch form of its timing (batched, graphs
-    of 50 steps), per field against the oracle."""
+    of 50 steps), per field against the oracle; reconstruction and interpolation forms."""
     import oracle_jobs
-    pr, steps = oracle_jobs.full_length_cases()["c4"]
+    pr, steps = oracle_jobs.full_length_cases()[case]
     pr = with_precision(pr, prec)
     s = solver([pr], graph_steps=50)
     s.batch_step(steps)
-    errs = _field_report("c4", prec, pr, s.state(0), full_refs.get("c4"))
+    errs = _field_report(case, prec, pr, s.state(0), full_refs.get(case))
     assert (errs < tol(prec, pr)).all(), errs
 
 
+@pytest.mark.parametrize("case", ["c2", "c2_chain"])
 @pytest.mark.parametrize("prec", ["fp64", "fp32c"])
-def test_full_c2(torch, full_refs, prec):
+def test_full_c2(torch, full_refs, prec, case):
     """The reactive NS flame at its full size and length (N 8192, P 64, FD8 with the
-    3-level halo, delays up to 4, RK4, 2000 steps), graphs of 50 steps; delay logs of
-    the last 64 steps bit-exact."""
+    3-level halo, delays up to 4, RK4, 2000 steps), graphs of 50 steps, flux and
+    chain-rule forms; delay logs of the last 64 steps bit-exact."""
     import oracle_jobs
-    pr, steps = oracle_jobs.full_length_cases()["c2"]
+    pr, steps = oracle_jobs.full_length_cases()[case]
     pr = with_precision(pr, prec)
     s = solver([pr], graph_steps=50, log_steps=64)
     s.batch_step(steps)
-    errs = _field_report("c2", prec, pr, s.state(0), full_refs.get("c2"))
+    errs = _field_report(case, prec, pr, s.state(0), full_refs.get(case))
     assert (errs < tol(prec, pr)).all(), errs
     # the delays of the last 64 steps against the oracle's generator (one draw per PE and
     # step, both sides); this late every delay is used as drawn
