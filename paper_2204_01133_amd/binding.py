@@ -92,8 +92,12 @@ def describe(pr) -> AtProblemDesc:
 
 
 def make_opts(**kw) -> AtRunOpts:
+    """Run options by field name of at_run_opts; an unknown name raises."""
     o = AtRunOpts()
+    known = {name for name, _ in AtRunOpts._fields_ if name != "reserved"}
     for k, v in kw.items():
+        if k not in known:
+            raise TypeError(f"unknown run option {k!r} (known: {', '.join(sorted(known))})")
         setattr(o, k, int(v))
     return o
 

@@ -35,3 +35,36 @@ def test_stale_library_refused(monkeypatch):
     monkeypatch.setattr(B, "source_hash", lambda: "0000000000000000")
     with pytest.raises(RuntimeError, match="not built from the current sources"):
         binding.load_library()
+
+
+def test_unknown_run_option_raises():
+    assert binding.make_opts(tile_points=512, halo_lds=1).tile_points == 512
+    with pytest.raises(TypeError, match="unknown run option 'tile_point'"):
+        binding.make_opts(tile_point=512)
+
+
+@pytest.mark.parametrize("cname,ctype", [("at_problem_desc", binding.AtProblemDesc),
+                                         ("at_run_opts", binding.AtRunOpts)])
+def test_binding_structs_match_the_header(tmp_path, cname, ctype):
+    """Every field of the ctypes structures at the offset the C compiler gives it, and the
+    same total size (a C program built here against include/at.h prints them)."""
+    import ctypes
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    src = tmp_path / "layout.c"
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "at.h"', "int main(void) {",
+             f'    printf("size %zu\\n", sizeof({cname}));']
+    for name, _ in ctype._fields_:
+        lines.append(f'    printf("{name} %zu\\n", offsetof({cname}, {name}));')
+    lines += ["    return 0;", "}"]
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c99", "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)], check=True)
+    out = dict(l.split() for l in subprocess.run([str(exe)], check=True, capture_output=True,
+                                                 text=True).stdout.splitlines())
+    assert int(out["size"]) == ctypes.sizeof(ctype)
+    for name, _ in ctype._fields_:
+        assert int(out[name]) == getattr(ctype, name).offset, name
