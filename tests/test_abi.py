@@ -1,5 +1,6 @@
 """The C ABI without a GPU: libat.so loads, exports every entry point that
-include/at.h declares, and the binding refuses a library built from other sources.
+include/at.h declares, and the binding refuses a library built from other sources;
+the ctypes structures of libat and of the oracle's library match their headers.
 No compute call is made here."""
 import os
 import re
@@ -43,26 +44,38 @@ def test_unknown_run_option_raises():
         binding.make_opts(tile_point=512)
 
 
-@pytest.mark.parametrize("cname,ctype", [("at_problem_desc", binding.AtProblemDesc),
-                                         ("at_run_opts", binding.AtRunOpts)])
-def test_binding_structs_match_the_header(tmp_path, cname, ctype):
-    """Every field of the ctypes structures at the offset the C compiler gives it, and the
-    same total size (a C program built here against include/at.h prints them)."""
+ORACLE_HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "oracle", "at_oracle.h")
+
+
+def _oracle_problem():
+    import oracle
+    return oracle.OrcProblem
+
+
+@pytest.mark.parametrize("cname,ctype,header", [("at_problem_desc", lambda: binding.AtProblemDesc, HEADER),
+                                                ("at_run_opts", lambda: binding.AtRunOpts, HEADER),
+                                                ("orc_problem", _oracle_problem, ORACLE_HEADER)],
+                         ids=["at_problem_desc", "at_run_opts", "orc_problem"])
+def test_binding_structs_match_the_header(tmp_path, cname, ctype, header):
+    """Every field of the ctypes structures (of libat and of the oracle's library) at the
+    offset the C compiler gives it, and the same total size (a C program built here
+    against the header prints them)."""
     import ctypes
+    ctype = ctype()
     import shutil
     import subprocess
     cc = shutil.which("gcc") or shutil.which("cc")
     if cc is None:
         pytest.skip("no C compiler")
     src = tmp_path / "layout.c"
-    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "at.h"', "int main(void) {",
+    lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{os.path.basename(header)}"', "int main(void) {",
              f'    printf("size %zu\\n", sizeof({cname}));']
     for name, _ in ctype._fields_:
         lines.append(f'    printf("{name} %zu\\n", offsetof({cname}, {name}));')
     lines += ["    return 0;", "}"]
     src.write_text("\n".join(lines) + "\n")
     exe = tmp_path / "layout"
-    subprocess.run([cc, "-std=c99", "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)], check=True)
+    subprocess.run([cc, "-std=c99", "-I", os.path.dirname(header), str(src), "-o", str(exe)], check=True)
     out = dict(l.split() for l in subprocess.run([str(exe)], check=True, capture_output=True,
                                                  text=True).stdout.splitlines())
     assert int(out["size"]) == ctypes.sizeof(ctype)
