@@ -265,9 +265,10 @@ int at_query(const at_ctx* ctx, int key, int64_t* value);
 void* at_stream(const at_ctx* ctx);
 
 /* (No passage: interface housekeeping.)  Text of an error code; of the context's
- * last error (its planner or HIP message); release of the context and of what
- * at_bind created (streams, events, graphs; the caller's workspace stays the
- * caller's). */
+ * last error (its planner or HIP message; with a null context, the planner's
+ * message of the calling thread's last failed at_init, which returns no context);
+ * release of the context and of what at_bind created (streams, events, graphs;
+ * the caller's workspace stays the caller's). */
 const char* at_strerror(int code);
 const char* at_last_error(const at_ctx* ctx);
 void at_free(at_ctx* ctx);

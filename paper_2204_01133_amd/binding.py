@@ -215,7 +215,8 @@ class ATSolver:
     def _check(self, rc: int, h="self"):
         if rc != 0:
             handle = self._h if h == "self" else None
-            msg = self.L.at_last_error(handle).decode() if handle else self.L.at_strerror(rc).decode()
+            # without a context (a failed at_init), the planner's message of this thread
+            msg = self.L.at_last_error(handle).decode() or self.L.at_strerror(rc).decode()
             raise ATError(rc, msg)
 
     def close(self):

@@ -251,14 +251,21 @@ int build_graph(at_ctx* c, int len) {
 
 extern "C" {
 
+// the planner's message of the calling thread's last failed at_init
+thread_local std::string g_init_err;
+
 int at_init(const at_problem_desc* probs, int n_probs, const at_run_opts* opts, at_ctx** out,
             size_t* workspace_bytes) {
-    if (!out || !workspace_bytes) return AT_EINVAL;
+    g_init_err.clear();
+    if (!out || !workspace_bytes) {
+        g_init_err = "null output argument";
+        return AT_EINVAL;
+    }
     *out = nullptr;
     at_ctx* c = new at_ctx();
     int rc = make_plan(probs, n_probs, opts, c->plan, c->err);
     if (rc) {
-        fprintf(stderr, "at_init: %s\n", c->err.c_str());
+        g_init_err = c->err;                 // for at_last_error(NULL) on this thread
         delete c;
         return rc;
     }
@@ -597,7 +604,7 @@ const char* at_strerror(int code) {
     return "unknown error";
 }
 
-const char* at_last_error(const at_ctx* c) { return c ? c->err.c_str() : "no context"; }
+const char* at_last_error(const at_ctx* c) { return c ? c->err.c_str() : g_init_err.c_str(); }
 
 void at_free(at_ctx* c) {
     if (!c) return;

@@ -81,3 +81,21 @@ def test_binding_structs_match_the_header(tmp_path, cname, ctype, header):
     assert int(out["size"]) == ctypes.sizeof(ctype)
     for name, _ in ctype._fields_:
         assert int(out[name]) == getattr(ctype, name).offset, name
+
+
+def test_failed_init_leaves_its_message():
+    """A plan that at_init refuses returns no context; at_last_error(NULL) then gives the
+    planner's message (host code only: the plan fails before any HIP call)."""
+    import ctypes
+    import at_workloads as W
+    L = binding.load_library()
+    h = ctypes.c_void_p()
+    nbytes = ctypes.c_size_t()
+    opts = binding.make_opts()
+    big = W.adv_diff_c1(n=8194, p=2, kmax=3)
+    arr = (binding.AtProblemDesc * 1)(binding.describe(big))
+    rc = L.at_init(arr, 1, ctypes.byref(opts), ctypes.byref(h), ctypes.byref(nbytes))
+    assert rc == binding.AT_EUNSUPPORTED and not h.value
+    assert b"exceeds the tile limit" in L.at_last_error(None)
+    rc = L.at_init(arr, 0, ctypes.byref(opts), ctypes.byref(h), ctypes.byref(nbytes))
+    assert rc == binding.AT_EINVAL and L.at_last_error(None) == b"no problems"

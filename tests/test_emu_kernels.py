@@ -175,3 +175,18 @@ def test_emu_run_options_agree_bitwise(prec, opts):
         for s in range(1, 5):
             c.rk_stage(s)
     assert np.array_equal(a.state(0), c.state(0))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32c"])
+def test_largest_scalar_pe_in_emulation(prec):
+    """The scalar FD kind's largest PE (4096 points, one large-class tile) under the bounds
+    checks of the emulation, against the oracle; 4097 points are refused."""
+    pr = W.adv_diff_c1(n=8192, p=2, kmax=3).replace(precision=prec)
+    e = at_emu.Emu([pr])
+    assert e.query(1) == 2
+    e.step(3)
+    o = oracle.Oracle(pr.replace(precision="fp64"))
+    o.step(3)
+    assert norm_err(pr, e.state(0), o.state()) < tol(prec)
+    with pytest.raises(at_emu.EmuError, match="exceeds the tile limit 4096"):
+        at_emu.Emu([pr.replace(n=8194, q0=np.zeros((1, 8194)))])

@@ -449,3 +449,39 @@ def test_domains_shorter_than_a_window(torch, prec, n, p):
     s = solver([pr])
     s.batch_step(10)
     assert norm_err(pr, s.state(0), _oracle(pr, 10).state()) < tol(prec)
+
+
+# the largest PE each kind takes (a tile of the large points-per-thread class: 256
+# threads x 16 points for the scalar FD kind, x 4 for the Euler WENO and reacting NS kinds)
+LARGEST_PE = [("adr_fd4", lambda: W.adv_diff_c1(n=8192, p=2, kmax=3), 4096),
+              ("sod_weno5", lambda: W.euler_sod_c4(n=2048, p=2), 1024),
+              ("flame_fd8", lambda: W.reactive_ns_c2(n=2048, p=2, kmax=2), 1024)]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32c"])
+@pytest.mark.parametrize("name,make,limit", LARGEST_PE, ids=[c[0] for c in LARGEST_PE])
+def test_largest_pe_of_each_kind(torch, name, make, limit, prec):
+    """A PE at the tile limit runs (against the oracle); one point more is refused."""
+    from paper_2204_01133_amd import ATError
+    pr = with_precision(make(), prec)
+    assert pr.n // pr.p == limit
+    s = solver([pr])
+    s.batch_step(6)
+    assert norm_err(pr, s.state(0), _oracle(pr, 6).state()) < tol(prec, pr)
+    over = pr.replace(n=pr.n + 2, q0=np.zeros((pr.q0.shape[0], pr.n + 2)))
+    with pytest.raises(ATError) as ei:
+        solver([over])
+    assert ei.value.code == -2 and "exceeds the tile limit" in str(ei.value)
+
+
+def test_empty_batch_and_zero_steps(torch):
+    """No problems is an argument error; zero steps change nothing."""
+    from paper_2204_01133_amd import ATError
+    with pytest.raises(ATError) as ei:
+        solver([])
+    assert ei.value.code == -1
+    pr = W.adv_diff_c1(n=256, p=8, kmax=3)
+    s = solver([pr])
+    s.batch_step(0)
+    s.step(0)
+    assert s.query(0) == 0 and np.array_equal(s.state(0), np.asarray(pr.q0, dtype=np.float64))
