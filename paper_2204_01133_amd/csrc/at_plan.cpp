@@ -318,7 +318,6 @@ int make_plan(const at_problem_desc* probs, int n_probs, const at_run_opts* opts
             const int cls = i < pi.ntiles_small ? 0 : 1;
             Group& g = plan.groups[pi.gid[cls]];
             g.jmax = std::max(g.jmax, pi.J);
-            if (std::find(g.probs.begin(), g.probs.end(), b) == g.probs.end()) g.probs.push_back(b);
             gtiles[pi.gid[cls]].push_back(plan.tiles_pm[pi.t0 + i]);
         }
     }

@@ -46,7 +46,6 @@ struct Group {
     int t0, ntiles;            // range in the batched (group-major) tile array
     int npts_max, npe_max, jmax;
     int64_t lds_bytes;
-    std::vector<int> probs;
 };
 
 struct Plan {

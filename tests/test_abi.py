@@ -99,3 +99,28 @@ def test_failed_init_leaves_its_message():
     assert b"exceeds the tile limit" in L.at_last_error(None)
     rc = L.at_init(arr, 0, ctypes.byref(opts), ctypes.byref(h), ctypes.byref(nbytes))
     assert rc == binding.AT_EINVAL and L.at_last_error(None) == b"no problems"
+
+
+def test_planning_scales_to_large_batches():
+    """at_init plans 50,000 small problems (one tile each or more) in well under a second
+    per 10,000 problems: no step of the planner is quadratic in the batch (host code only)."""
+    import ctypes
+    import time
+    import at_workloads as W
+    L = binding.load_library()
+    n = 50000
+    prs = W.batched_adr_c3(steps=10, n_problems=n, n_min=256, n_max=512)
+    arr = (binding.AtProblemDesc * n)(*[binding.describe(p) for p in prs])
+    h = ctypes.c_void_p()
+    nbytes = ctypes.c_size_t()
+    opts = binding.make_opts()
+    t0 = time.perf_counter()
+    rc = L.at_init(arr, n, ctypes.byref(opts), ctypes.byref(h), ctypes.byref(nbytes))
+    dt = time.perf_counter() - t0
+    try:
+        assert rc == binding.AT_OK
+        tiles = ctypes.c_int64()
+        assert L.at_query(h, binding.Q_NUM_TILES, ctypes.byref(tiles)) == 0 and tiles.value >= n
+        assert dt < 5.0, dt
+    finally:
+        L.at_free(h)
