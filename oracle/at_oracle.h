@@ -42,6 +42,12 @@
  *     paper cites (Thompson 1987; Poinsot & Lele 1992) with the incoming wave
  *     amplitudes set to zero.  The ends are not PE boundaries: no delays.
  *
+ * Pins (tests/test_oracle_*.py) fix every part above against closed forms, the
+ * paper's printed stencils and tables, or brute force.  Parity unpinned: the
+ * long-run accuracy of the one-step-chemistry flame (reactive NS over many
+ * steps), whose terms are pinned one by one but whose composition has no closed
+ * form; the detonation's composition is pinned by the Chapman-Jouguet speed.
+ *
  * Errors: every int-returning function returns ORC_OK (0) or a negative code.
  * Ownership: the caller owns every pointer it passes; the run owns its own
  * memory and frees it in orc_free.
