@@ -485,3 +485,18 @@ def test_empty_batch_and_zero_steps(torch):
     s.batch_step(0)
     s.step(0)
     assert s.query(0) == 0 and np.array_equal(s.state(0), np.asarray(pr.q0, dtype=np.float64))
+
+
+@pytest.mark.parametrize("scheme", ["weno5", "weno5i"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32c", "fp32"])
+def test_detonation_front_at_the_chapman_jouguet_speed(torch, prec, scheme):
+    """The oracle's Chapman-Jouguet pin run on the GPU: the driver-initiated detonation (AT,
+    delays up to 4) runs at the CJ speed within 3 %, its front within a grid point of the
+    oracle's at both times."""
+    import test_oracle_detonation as D
+    pr = with_precision(D._problem(512, "at", 4, scheme=scheme), prec)
+    s = solver([pr])
+    d = D.front_speed(pr, run=(s.batch_step, lambda: s.state(0)))
+    assert abs(d / D.D_CJ - 1.0) < 0.03, (d, D.D_CJ)
+    one_cell = 1.0 / (pr.n * 0.03)                 # one grid point over the timed interval
+    assert abs(d - D.front_speed(pr.replace(precision="fp64"))) <= 2 * one_cell

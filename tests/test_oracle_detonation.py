@@ -41,16 +41,20 @@ def _problem(n, mode="sync", kmax=0, scheme="weno5"):
                      kmax=kmax, gamma=GAMMA, q=QH, ea=EA, b=B, steps=10)
 
 
-def front_speed(pr, t1=0.015, t2=0.045):
+def front_speed(pr, t1=0.015, t2=0.045, run=None):
     """Speed of the right-running front between t1 and t2 (None if there is no front:
-    the gas ahead has burnt everywhere)."""
-    o = oracle.Oracle(pr)
+    the gas ahead has burnt everywhere).  run: (step(k), state()) of another solver of
+    the same problem (default: the oracle)."""
+    if run is None:
+        o = oracle.Oracle(pr)
+        run = (o.step, o.state)
+    step, state = run
     pos, t = [], 0.0
     for ts in (t1, t2):
         k = int(round((ts - t) / pr.dt))
-        o.step(k)
+        step(k)
         t += k * pr.dt
-        q = o.state()
+        q = state()
         Y = q[3] / q[0]
         i0 = int(0.02 * pr.n) + 1
         ahead = np.nonzero(Y[i0:] > 0.5)[0]
