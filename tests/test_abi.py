@@ -124,3 +124,22 @@ def test_planning_scales_to_large_batches():
         assert dt < 5.0, dt
     finally:
         L.at_free(h)
+
+
+def test_missing_library_is_an_error(monkeypatch, tmp_path):
+    """No fallback: without libat.so the binding raises."""
+    monkeypatch.setattr(binding, "_lib", None)
+    monkeypatch.setattr(binding, "LIB_PATH", str(tmp_path / "libat.so"))
+    with pytest.raises(RuntimeError, match="libat.so not built"):
+        binding.load_library()
+
+
+def test_solver_without_a_gpu_is_an_error():
+    """The solver has no CPU path: on a host without a visible GPU it raises."""
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is visible")
+    import at_workloads as W
+    from paper_2204_01133_amd import ATSolver
+    with pytest.raises(RuntimeError, match="needs a GPU"):
+        ATSolver([W.adv_diff_c1(n=64, p=4)])
