@@ -558,6 +558,9 @@ AT_HD AT_FI double arrhenius(const PhysP& P, const double* q) {
 }
 
 // Reciprocal: the hardware's approximation (1 ulp) in FP32 on the GPU, a division otherwise.
+// fused multiply-add a b + c (one rounding) in either precision
+AT_HD AT_FI float fma_r(float a, float b, float c) { return fmaf(a, b, c); }
+AT_HD AT_FI double fma_r(double a, double b, double c) { return fma(a, b, c); }
 AT_HD AT_FI double rcp_w(double x) { return 1.0 / x; }
 AT_HD AT_FI float rcp_w(float x) {
 #if defined(__HIP_DEVICE_COMPILE__)
@@ -622,10 +625,11 @@ AT_HD AT_FI R weno5_corr(R epsh, R v0, R v1, R v2, R v3, R v4) {
     const R d01 = v1 - v0, d12 = v2 - v1, d23 = v3 - v2, d34 = v4 - v3;
     const R a0 = d12 - d01, a1 = d23 - d12, a2 = d34 - d23;
     const R b0 = R(3) * d12 - d01, b1 = d12 + d23, b2 = d34 - R(3) * d23;
+    // e_k = epsh + a_k^2 + (3/13) b_k^2, as two fused multiply-adds after one product
     const R k = R(3.0 / 13.0);
-    const R e0 = epsh + (a0 * a0 + k * (b0 * b0));
-    const R e1 = epsh + (a1 * a1 + k * (b1 * b1));
-    const R e2 = epsh + (a2 * a2 + k * (b2 * b2));
+    const R e0 = fma_r(a0, a0, fma_r(k * b0, b0, epsh));
+    const R e1 = fma_r(a1, a1, fma_r(k * b1, b1, epsh));
+    const R e2 = fma_r(a2, a2, fma_r(k * b2, b2, epsh));
     R r0, r1, r2;
     if constexpr (INTERP) {
         r0 = R(7) * d12 - R(3) * d01;
